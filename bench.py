@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of the relaxation step on one MI355X: grid-point updates/s and HBM roofline.
+
+Workload: the 256^3 periodic box [0, 2 pi)^3 holding the ABC Beltrami field (A = B = C = 1),
+positions x0 = X + a seeded divergence-free Fourier displacement (|k| <= 3, max 0.1, seed 5).
+A step is one accepted adaptive Cash-Karp RK5(4) step (six fused stage sweeps plus the
+device step control; rejected attempts are redone inside and counted in the time).
+
+    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed|both]
+
+Prints one JSON line.  value = N * accepted steps / wall time of the timed relax_step
+call (inputs resident in HBM), FP64.  The FP32-mixed figures are in "fp32_mixed".
+"roofline" is the dominant kernel's algorithmic bytes per launch over its average launch
+duration (HIP events around each launch), against the 8 TB/s HBM3E peak.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "grid-point updates/s (FP64 vs FP32-mixed) + % HBM roofline at 256^3"
+
+# algorithmic HBM bytes per node of each stage sweep (read x_n, k_1..k_{s-1}, B0; write k_s;
+# stage 6 writes x_{n+1} instead of k_6) -- FP64 and FP32-mixed (x in FP64, k and B0 in FP32)
+BYTES_FP64 = [72, 96, 120, 144, 168, 192]
+BYTES_MIXED = [48, 60, 72, 84, 96, 120]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
+    cfg = R.make_config(w.grid, precision=precision, dt0=dt0, tol=tol, adaptive=True)
+    x0 = torch.from_numpy(w.x0).cuda()
+    B0 = torch.from_numpy(w.B0).cuda()
+    N = w.grid.N
+    out = {}
+    with R.Relaxation(cfg, x0, B0) as r:
+        del x0, B0
+        log(f"precision {precision}: warmup {warmup} steps")
+        r.step(warmup, diag=False)
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        log(f"precision {precision}: timed {steps} steps")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record(r.stream)
+        diag = r.step(steps)
+        stop.record(r.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = start.elapsed_time(stop)
+        rejects = sum(d["rejects"] for d in diag)
+        # second pass with every launch bracketed by HIP events, for the per-kernel figures
+        log(f"precision {precision}: profiled {steps} steps")
+        r.profile(True)
+        r.step(steps, diag=False)
+        prof = r.profile(False)
+        fin = r.diagnostics()
+    bytes_node = BYTES_FP64 if precision == R.RELAX_FP64 else BYTES_MIXED
+    kernels = {}
+    for s in range(2, 7):  # stage 1 is skipped on retries, so its launch count overstates work
+        ms, n = prof[f"stage{s}"]
+        avg = ms / n
+        gbs = bytes_node[s - 1] * N / (avg * 1e-3) / 1e9
+        kernels[f"stage{s}"] = {"avg_ms": avg, "launches": n, "GB/s": gbs}
+    ms1, n1 = prof["stage1"]
+    kernels["stage1"] = {"total_ms": ms1, "launches": n1}
+    kernels["control"] = {"total_ms": prof["control"][0], "launches": prof["control"][1]}
+    dom = max((k for k in kernels if "avg_ms" in kernels[k]), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    achieved = kernels[dom]["GB/s"]
+    step_bytes = sum(bytes_node) * N
+    out.update(
+        value=N * steps / wall,
+        ms_per_step=wall * 1e3 / steps,
+        event_ms_per_step=ev_ms / steps,
+        rejects=rejects,
+        dt_last=diag[-1]["dt"],
+        xi_first=diag[0]["xi"],
+        xi_last=diag[-1]["xi"],
+        E_first=diag[0]["E_M"],
+        E_last=diag[-1]["E_M"],
+        fp64_final_xi=fin["xi"],
+        step_GBs=step_bytes * steps / wall / 1e9,
+        kernels=kernels,
+        roofline={"bound": "hbm", "kernel": f"stage_kernel<{dom[-1]}> ({'fp64' if precision == 0 else 'fp32-mixed'})",
+                  "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                  "traffic": None},
+    )
+    return out
+
+
+def cpu_baseline(w, steps, dt):
+    import oracle
+    log(f"cpu baseline: oracle, {steps} fixed-dt steps on the full grid, {oracle.threads()} threads")
+    t0 = time.perf_counter()
+    oracle.run(w.grid, w.x0, w.B0, steps, dt=dt, mode=oracle.MODE_FIXED)
+    sec = time.perf_counter() - t0
+    return {"value": w.grid.N * steps / sec, "unit": "grid-point updates/s", "cores": oracle.threads(),
+            "kind": "oracle", "sample": f"{steps} fixed-dt Cash-Karp steps of the full {w.name} grid "
+                                        f"({sec:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="grid points per axis of the ABC box")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--dt0", type=float, default=1e-3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the relaxation step has no multi-GPU path in this build "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1405_0942_amd as R
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    R.lib()  # fail loudly if the HIP library is missing
+    log(f"building inputs abc_{args.n}^3")
+    w = W.abc_box(args.n)
+    res = {}
+    if args.precision in ("fp64", "both"):
+        res["fp64"] = run_precision(R, torch, w, R.RELAX_FP64, args.steps, args.warmup, args.tol, args.dt0)
+    if args.precision in ("mixed", "both"):
+        res["mixed"] = run_precision(R, torch, w, R.RELAX_FP32_MIXED, args.steps, args.warmup, args.tol, args.dt0)
+    main_key = "fp64" if "fp64" in res else "mixed"
+    m = res[main_key]
+    line = {
+        "metric": METRIC,
+        "value": m["value"],
+        "unit": "grid-point updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_key == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: ABC field A=B=C=1 on the periodic box [0,2pi)^3, x0 = X + "
+                               f"divergence-free |k|<=3 displacement (max 0.1, seed 5)",
+                   "grid": list(w.grid.n), "step": "one accepted adaptive Cash-Karp RK5(4) step",
+                   "tol": args.tol, "rejects_in_timed_steps": m["rejects"],
+                   "step_hbm_GBs_algorithmic": m["step_GBs"],
+                   "step_hbm_frac": m["step_GBs"] / HBM_PEAK_GBS},
+        "roofline": m["roofline"],
+        "kernels": m["kernels"],
+    }
+    if main_key == "fp64" and "mixed" in res:
+        mm = res["mixed"]
+        line["fp32_mixed"] = {"value": mm["value"], "ms_per_step": mm["ms_per_step"], "dtype": "f64+f32",
+                              "rejects_in_timed_steps": mm["rejects"], "roofline": mm["roofline"],
+                              "step_hbm_GBs_algorithmic": mm["step_GBs"], "kernels": mm["kernels"],
+                              "E_last_rel_diff_vs_fp64": abs(mm["E_last"] - m["E_last"]) / abs(m["E_last"])}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, dt=args.dt0)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,144 @@
+/*
+ * relax.h -- C ABI of the MI355X (gfx950) Lagrangian mimetic magneto-frictional relaxation
+ * step (Candelaresi, Pontin & Hornig, "Mimetic Methods for Lagrangian Relaxation of
+ * Magnetic Fields").
+ *
+ * The state is the Lagrangian map x(X, t) sampled on a logically rectangular, node-centred
+ * grid of reference positions X (Sec. 1, eq. "x integration").  The field is frozen in:
+ * at every node B = F B0 / det F with F = dx/dX (Sec. 2.1, eq. "B transformation").  The
+ * current J = curl B is the Stokes-loop mimetic operator of Sec. 2.2 (eqs. "current
+ * discrete", "four surfaces", "sum of triangles", "current matrix equation") and the
+ * velocity is the magneto-frictional u = gamma J x B (Sec. 1, eq. "magneto friction").
+ * x is advanced by the fifth-order adaptive Cash-Karp Runge-Kutta method with the
+ * step-size rule of Sec. 2.4 (eq. "time stepping").  Boundaries are line-tied or
+ * periodic with shifted ghost positions (Sec. 2.5).
+ *
+ * Conventions
+ *  - Fields are structure-of-arrays FP64 [3][nz][ny][nx], x fastest: component c of node
+ *    (i, j, k) is at c*N + (k*ny + j)*nx + i with N = nx*ny*nz.
+ *  - Pointers named d_* are device pointers (HIP), owned by the caller.  The library never
+ *    allocates device memory: all its device state lives in the caller's workspace.
+ *  - hip_stream is a hipStream_t (may be NULL for the default stream).  All work is
+ *    enqueued on it; a call returns after the host copies it documents.
+ *  - Every function returns RELAX_OK (0) or a negative RELAX_E_* code and never throws.
+ *    After RELAX_E_FOLD, RELAX_E_DT, RELAX_E_NAN or RELAX_E_HIP a context is failed: every
+ *    further call except relax_get_state, relax_set_state, relax_last_error and
+ *    relax_destroy returns RELAX_E_STATE.
+ *  - Calls on one context must not overlap; different contexts are independent.
+ */
+#ifndef RELAX_H
+#define RELAX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RELAX_OK = 0,
+  RELAX_E_ARG = -1,   /* invalid argument or configuration */
+  RELAX_E_HIP = -2,   /* a HIP runtime call failed */
+  RELAX_E_FOLD = -3,  /* min det F <= 0: folded grid (the paper's breakdown, Sec. 4.4) */
+  RELAX_E_DT = -4,    /* step rejected below dt_min (dt collapse, Sec. 4.4) */
+  RELAX_E_NAN = -5,   /* non-finite energy, residual or error estimate */
+  RELAX_E_STATE = -6, /* context failed earlier, or no recorded trajectory */
+  RELAX_E_SPACE = -7  /* workspace too small */
+};
+
+enum { RELAX_LINE_TIED = 0, RELAX_PERIODIC = 1 };
+enum { RELAX_FP64 = 0, RELAX_FP32_MIXED = 1 };
+
+typedef struct {
+  int n[3];             /* nodes along x, y, z; each >= 4 */
+  double h[3];          /* reference spacing dX, dY, dZ (> 0).  Periodic period P_a = n_a h_a */
+  int bc[3];            /* per axis RELAX_LINE_TIED or RELAX_PERIODIC (Sec. 2.5) */
+  int precision;        /* RELAX_FP64, or RELAX_FP32_MIXED: stage vectors, B0 copy and the
+                           stencil past the Jacobian in FP32; positions, det F, the energy and
+                           residual reductions and the step control in FP64 */
+  double gamma;         /* friction coefficient (the paper uses 1, Sec. 2.1) */
+  double dt0;           /* first step size (> 0) */
+  double dt_min;        /* a rejected step below this fails with RELAX_E_DT */
+  double tol;           /* Lambda_0: bound on the max-norm error estimate of x per step */
+  int adaptive;         /* 1: the step-size rule of Sec. 2.4; 0: fixed dt = dt0 */
+  int record;           /* 1: keep the dt of every step and x every checkpoint_every steps
+                           for relax_backward */
+  int checkpoint_every; /* checkpoint interval c (>= 1) when record = 1 */
+  double xi_null_tau;   /* xi skips nodes with |B|^2 <= xi_null_tau * max |B0|^2 (e.g. 1e-12) */
+} relax_config;
+
+/* Per accepted step, evaluated at the state the step starts from (pre-step). */
+typedef struct {
+  double t;       /* time of the state */
+  double dt;      /* accepted step size */
+  double E_M;     /* magnetic energy 1/2 sum zeta |B|^2 det F dX dY dZ (eq. "magnetic energy") */
+  double xi;      /* max over interior nodes of |J x B| / |B|^2 (Sec. 4.1) */
+  double R2;      /* 1/2 sum_interior det F |J x B|^2 dX dY dZ (smooth force residual) */
+  double Lambda;  /* error estimate max |x5 - x4| of the accepted attempt */
+  double min_det; /* min det F over all nodes */
+  int rejects;    /* rejected attempts before acceptance */
+} relax_diag;
+
+/* Bytes of device workspace a context with this configuration needs.  K_record is the
+ * number of steps relax_backward may later differentiate through (0 if record = 0).
+ * Returns 0 for an invalid configuration. */
+size_t relax_workspace_bytes(const relax_config* cfg, int K_record);
+
+/* Create a context.  d_x0 (initial positions) and d_B0 (initial field at the nodes,
+ * B(X, 0)) are [3][nz][ny][nx] FP64 device arrays; they are copied, so the caller may
+ * free them afterwards.  d_workspace (>= relax_workspace_bytes(cfg, K_record) bytes,
+ * 256-byte aligned) belongs to the context until relax_destroy.  A folded x0 returns
+ * RELAX_E_FOLD and no context.  Synchronises hip_stream once. */
+int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const double* d_B0,
+               void* d_workspace, size_t workspace_bytes, void* hip_stream, void** out_ctx);
+
+/* Advance by K accepted Cash-Karp steps (rejected attempts are redone inside).  If
+ * host_diag is not NULL it receives K entries (host memory), one per accepted step.
+ * On an error the steps completed before it are kept and reported in *steps_done (may be
+ * NULL).  Blocks until the steps are done. */
+int relax_step(void* ctx, int K, relax_diag* host_diag, int* steps_done);
+
+/* FP64 diagnostics sweep of the current positions (also for a mixed-precision context):
+ * fills t, dt (next step size), E_M, xi, R2, min_det; Lambda and rejects are 0. */
+int relax_diagnostics(void* ctx, relax_diag* out);
+
+/* Velocity u = gamma J x B of the current positions (Sec. 1, eq. "magneto friction", with
+ * J the mimetic current of Sec. 2.2), evaluated in FP64 (also for a mixed-precision
+ * context) into d_u_out (device, [3][nz][ny][nx], overwritten; zero on line-tied faces).
+ * Blocks until done. */
+int relax_velocity(void* ctx, double* d_u_out);
+
+/* Reverse-mode gradient through the recorded fixed-dt trajectory (record = 1):
+ * d(seed_EM * E_M(x_K) + seed_R2 * R2(x_K)) / d(x0, B0), where x_K is the current state
+ * and x0 the state at init / relax_set_state.  d_grad_x0, d_grad_B0: [3][nz][ny][nx] FP64
+ * device arrays (overwritten).  Returns RELAX_E_STATE if nothing was recorded. */
+int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0, double* d_grad_B0);
+
+/* Copy the current positions to d_x_out (device, [3][nz][ny][nx] FP64) and read t and the
+ * next step size; any output may be NULL. */
+int relax_get_state(void* ctx, double* d_x_out, double* t, double* dt);
+
+/* Replace the positions (device array, copied), t and dt; clears a failed state and the
+ * recorded trajectory.  A folded state returns RELAX_E_FOLD. */
+int relax_set_state(void* ctx, const double* d_x_in, double t, double dt);
+
+/* Per-kernel timing.  Returns the totals accumulated since the previous call (then resets
+ * them) and switches timing on (on = 1) or off (0).  While on, relax_step brackets each
+ * kernel launch with HIP events on hip_stream.  ms_out[7] / launches_out[7] (host, may be
+ * NULL): index 0..5 = the six Runge-Kutta stage sweeps, 6 = the step-control kernel. */
+int relax_profile(void* ctx, int on, double* ms_out, long long* launches_out);
+
+/* Short English text of a status code (static storage). */
+const char* relax_strerror(int code);
+
+/* Text of the last error recorded on this context ("" if none). */
+const char* relax_last_error(void* ctx);
+
+/* Release the context (host memory only; the workspace goes back to the caller). */
+void relax_destroy(void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RELAX_H */

@@ -42,6 +42,11 @@ def lib():
     L.orc_run.argtypes = [i3, d3, i3, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int,
                           _dp, _dp, d3, d3, C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
     L.orcz_run_fixed.argtypes = [i3, d3, i3, C.c_double, C.c_int, _dp, _zp, _zp, C.c_void_p, C.c_void_p]
+    L.orc_rhs_sampled.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_long,
+                                  np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS"), _dp]
+    L.orc_rhs_sampled.restype = C.c_int
+    L.orc_threads.argtypes = []
+    L.orc_threads.restype = C.c_int
     L.orc_tableau.argtypes = [_dp, _dp, _dp]
     L.orc_tableau.restype = None
     for f in (L.orc_fields, L.orc_diagnostics, L.orc_ck_attempt, L.orc_controller, L.orc_run, L.orcz_run_fixed):
@@ -86,6 +91,14 @@ def fields(grid, x, B0, gamma=1.0):
     return {"B": B, "det": det, "J": J, "u": u}
 
 
+def rhs_sampled(grid, x, B0, nodes, gamma=1.0):
+    """u at the given flat node indices (k*ny + j)*nx + i; returns (len(nodes), 3)."""
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    out = np.zeros((len(nodes), 3))
+    _check(lib().orc_rhs_sampled(*_g(grid), gamma, _f64(x), _f64(B0), len(nodes), nodes, out))
+    return out
+
+
 def diagnostics(grid, x, B0, tau_B2=0.0):
     """{E_M, xi, min_det, R2, skipped} of positions x."""
     out = np.zeros(5)
@@ -101,6 +114,11 @@ def ck_attempt(grid, x, B0, dt, gamma=1.0, want_k=False):
     k = np.empty((6,) + x.shape) if want_k else None
     _check(lib().orc_ck_attempt(*_g(grid), gamma, x, B0, float(dt), xn, C.byref(lam), _ptr(k)))
     return (xn, lam.value, k) if want_k else (xn, lam.value)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's sweeps use."""
+    return int(lib().orc_threads())
 
 
 def tableau():

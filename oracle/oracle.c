@@ -42,6 +42,7 @@
  *   R9 no safety factor; when Lambda == 0 the step grows by 5x.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -166,6 +167,21 @@ static real_t det3(real_t M[3][3]) {
        + M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
 }
 
+/* B and Delta at one node */
+static void field_at(const grid_t *g, const real_t *x, const real_t *B0, const int p[3], real_t Bp[3], real_t *det) {
+  const long N = g->N;
+  const long m = node_id(g, p);
+  real_t F[3][3];
+  jacobian(g, x, p, F);
+  real_t D = det3(F);
+  if (det) *det = D;
+  for (int c = 0; c < 3; c++) {
+    real_t s = 0.0;
+    for (int jj = 0; jj < 3; jj++) s += F[c][jj] * B0[jj * N + m];
+    Bp[c] = s / D;
+  }
+}
+
 /* B and Delta at every node */
 static void pull_back(const grid_t *g, const real_t *x, const real_t *B0, real_t *B, real_t *det) {
   const long N = g->N;
@@ -175,15 +191,9 @@ static void pull_back(const grid_t *g, const real_t *x, const real_t *B0, real_t
       for (int i = 0; i < g->n[0]; i++) {
         int p[3] = {i, j, k};
         long m = node_id(g, p);
-        real_t F[3][3];
-        jacobian(g, x, p, F);
-        real_t D = det3(F);
-        det[m] = D;
-        for (int c = 0; c < 3; c++) {
-          real_t s = 0.0;
-          for (int jj = 0; jj < 3; jj++) s += F[c][jj] * B0[jj * N + m];
-          B[c * N + m] = s / D;
-        }
+        real_t Bp[3];
+        field_at(g, x, B0, p, Bp, &det[m]);
+        for (int c = 0; c < 3; c++) B[c * N + m] = Bp[c];
       }
 }
 
@@ -203,7 +213,9 @@ static void cross(const real_t a[3], const real_t b[3], real_t out[3]) {
   out[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-static void mimetic_current(const grid_t *g, const real_t *x, const real_t *B, const int p[3], real_t J[3]) {
+/* B == NULL: the vertex fields are pulled back from B0 on the spot (sampled evaluation) */
+static void mimetic_current(const grid_t *g, const real_t *x, const real_t *B, const real_t *B0, const int p[3],
+                            real_t J[3]) {
   const long N = g->N;
   real_t M[3][3], C[3];
   real_t xp[3];
@@ -220,9 +232,12 @@ static void mimetic_current(const grid_t *g, const real_t *x, const real_t *B, c
     for (int r = 0; r < 4; r++) {
       double s[3];
       long m = neighbour(g, p, off[r], s);
-      for (int c = 0; c < 3; c++) {
-        V[r][c] = x[c * N + m] + s[c];
-        BV[r][c] = B[c * N + m];
+      for (int c = 0; c < 3; c++) V[r][c] = x[c * N + m] + s[c];
+      if (B) {
+        for (int c = 0; c < 3; c++) BV[r][c] = B[c * N + m];
+      } else {
+        int q[3] = {(int)(m % g->n[0]), (int)((m / g->n[0]) % g->n[1]), (int)(m / ((long)g->n[0] * g->n[1]))};
+        field_at(g, x, B0, q, BV[r], NULL);
       }
     }
     real_t circ = 0.0, nA[3] = {0.0, 0.0, 0.0};
@@ -289,7 +304,7 @@ static void rhs(const grid_t *g, double gamma, const real_t *x, const real_t *B0
         real_t J[3] = {0.0, 0.0, 0.0}, f[3] = {0.0, 0.0, 0.0};
         if (!on_line_tied_face(g, p)) {
           real_t Bm[3] = {w->B[m], w->B[N + m], w->B[2 * N + m]};
-          mimetic_current(g, x, w->B, p, J);
+          mimetic_current(g, x, w->B, NULL, p, J);
           cross(J, Bm, f);
         }
         for (int c = 0; c < 3; c++) {
@@ -424,6 +439,29 @@ int orc_fields(const int n[3], const double h[3], const int bc[3], double gamma,
   return ORC_OK;
 }
 
+/* u = gamma J x B at the listed nodes only (flat node indices), for spot checks of grids
+ * too large for a full sweep.  u_out: [count][3]. */
+int orc_rhs_sampled(const int n[3], const double h[3], const int bc[3], double gamma, const double *x,
+                    const double *B0, long count, const long *nodes, double *u_out) {
+  grid_t g;
+  int rc = grid_init(&g, n, h, bc);
+  if (rc) return rc;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long s = 0; s < count; s++) {
+    const long m = nodes[s];
+    int p[3] = {(int)(m % g.n[0]), (int)((m / g.n[0]) % g.n[1]), (int)(m / ((long)g.n[0] * g.n[1]))};
+    double f[3] = {0.0, 0.0, 0.0};
+    if (!on_line_tied_face(&g, p)) {
+      double J[3], Bm[3];
+      field_at(&g, x, B0, p, Bm, NULL);
+      mimetic_current(&g, x, NULL, B0, p, J);
+      cross(J, Bm, f);
+    }
+    for (int c = 0; c < 3; c++) u_out[3 * s + c] = gamma * f[c];
+  }
+  return ORC_OK;
+}
+
 /* Diagnostics of positions x: out = {E_M, xi, min Delta, R2, skipped}. */
 int orc_diagnostics(const int n[3], const double h[3], const int bc[3], double tau_B2, const double *x,
                     const double *B0, double out[5]) {
@@ -468,6 +506,9 @@ int orc_ck_attempt(const int n[3], const double h[3], const int bc[3], double ga
   work_free(&w);
   return ORC_OK;
 }
+
+/* OpenMP threads the sweeps use */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* The Cash-Karp coefficients as stored: A (6x6, row s = stage), b5, b4. */
 void orc_tableau(double A[36], double b5[6], double b4[6]) {

@@ -1,0 +1,106 @@
+// relax_device.h -- internal types shared by the library's translation units (kernels and
+// the C-ABI glue).  Not part of the public interface (that is include/relax.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace relax {
+
+// ------------------------------------------------------------------------------------------
+// Tiling of the fused stage sweep.  One workgroup owns a TX x TY column of nodes in (x, y)
+// and marches up a z-chunk of TZ planes; one wave64 covers one x-row of the tile.
+// ------------------------------------------------------------------------------------------
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int NTHREADS = TX * TY;  // 256 = 4 waves
+constexpr int RX2 = TX + 4, RY2 = TY + 4;  // stage-input window (2-node halo)
+constexpr int RX1 = TX + 2, RY1 = TY + 2;  // pulled-back field window (1-node halo)
+constexpr int NPART = 8;                   // doubles per workgroup partial record
+constexpr int RING_CAP = 4096;             // per-call diagnostics ring entries
+
+enum { BC_LINE_TIED = 0, BC_PERIODIC = 1 };
+
+struct Geometry {
+  int n[3];          // nodes along x, y, z
+  int bc[3];         // BC_LINE_TIED / BC_PERIODIC per axis
+  double h[3];       // reference spacing
+  double inv2h[3];   // 1 / (2 h)
+  double period[3];  // n h (used on periodic axes)
+  long long N;       // number of nodes
+  double dV;         // hx hy hz
+  int tiles[3];      // tiles along x, along y, z-chunks
+  int tz;            // z-chunk length
+  int nblocks;       // tiles[0] * tiles[1] * tiles[2]
+};
+
+// Device-resident step state.  Written only by the control kernel (and by small set-up
+// kernels launched by the host on the same stream).
+struct Control {
+  double t, dt;              // time and step to try next
+  double tol, dt_min;        // Lambda_0, breakdown threshold
+  double gamma, tau_B2;      // friction coefficient, xi null-guard threshold on |B|^2
+  double dV;                 // hx hy hz
+  double E, xi, R2, min_det, nulls;  // diagnostics of the state x_n the current step starts from
+  double lambda;             // Lambda of the last attempt
+  int status;                // 0 or a (sticky) RELAX_E_* code
+  int cur;                   // index of the x buffer holding x_n
+  int accepted;              // accepted steps in the current relax_step chunk
+  int target;                // kernels stop doing work once accepted >= target
+  int need_k1;               // 1: k1 and the diagnostics of x_n are (re)computed by stage 1
+  int rejects;               // rejects in the current step
+  int adaptive;              // 1: step-size rule; 0: fixed dt
+  int record;                // 1: store dt per step and x every `ck_every` steps
+  int ck_every;              // checkpoint interval
+  int record_cap;            // capacity of the dt record (steps)
+  long long steps_total;     // accepted steps since init / set_state
+};
+
+// Arguments of every sweep kernel (passed by value in the kernarg segment).
+struct SweepArgs {
+  Geometry g;
+  const double* x[2];  // position buffers (x_n is x[ctl->cur])
+  double* xout[2];     // same buffers, writable (stage 6 writes x[1 - cur])
+  void* k[6];          // stage vectors k1..k5 (double, or float in mixed mode)
+  const void* B0;      // initial field (double, or float in mixed mode)
+  Control* ctl;
+  double* part;        // [nblocks][NPART] reduction partials of stage 1 / diagnostics
+  double* lam_part;    // [nblocks] Lambda partials of stage 6
+  double* ckpt;        // checkpoint store [slots][3N] (record mode), may be null
+  int ckpt_slots;
+  int diag_only;       // 1: diagnostics sweep of x[diag_buf] (no gating, no k written)
+  int diag_buf;
+  double* u_out;       // diagnostics sweep only: if not null, receives u(x) [3][N] (FP64)
+};
+
+// Cash-Karp RK5(4) coefficients (Cash & Karp 1990): stage rows a_sj, 5th and 4th order
+// weights.  (Constant tables of the integrator; compiled into the device code.)
+struct CK {
+  static constexpr double a[6][5] = {
+      {0, 0, 0, 0, 0},
+      {1.0 / 5.0, 0, 0, 0, 0},
+      {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
+      {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
+      {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
+      {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+  static constexpr double b5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+  static constexpr double b4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0,
+                                   277.0 / 14336.0, 1.0 / 4.0};
+};
+
+// ------------------------------------------------------------------------------------------
+// Launchers implemented in the kernel translation units
+// ------------------------------------------------------------------------------------------
+// stage s in 1..6; mixed selects float k / B0 storage
+hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st);
+hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st);  // FP64 sweep, diag_only
+hipError_t launch_control(Control* ctl, const double* part, const double* lam_part, int nblocks,
+                          double* ring, double* dt_record, hipStream_t st);
+hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out5, hipStream_t st);
+hipError_t launch_begin_chunk(Control* ctl, int target, hipStream_t st);
+hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t st);
+hipError_t launch_max_norm2(const double* v, long long N, double* out, hipStream_t st);
+
+}  // namespace relax
