@@ -100,6 +100,25 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
     return out
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Device-to-device copy of `mib` MiB (the runtime's blit kernel): GB/s counting read +
+    write bytes.  Also the known-size kernel the HBM byte counters are calibrated on."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    stop.record()
+    torch.cuda.synchronize()
+    sec = start.elapsed_time(stop) * 1e-3 / reps
+    del src, dst
+    return 2 * n * 8 / sec / 1e9
+
+
 def cpu_baseline(w, steps, dt):
     import oracle
     log(f"cpu baseline: oracle, {steps} fixed-dt steps on the full grid, {oracle.threads()} threads")
@@ -138,6 +157,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     R.lib()  # fail loudly if the HIP library is missing
+    copy_gbs = copy_bandwidth(torch)
+    log(f"device copy {copy_gbs:.0f} GB/s (read + write)")
     log(f"building inputs abc_{args.n}^3")
     w = W.abc_box(args.n)
     res = {}
@@ -168,6 +189,7 @@ def main():
                    "step_hbm_frac": m["step_GBs"] / HBM_PEAK_GBS},
         "roofline": m["roofline"],
         "kernels": m["kernels"],
+        "copy_GBs": copy_gbs,
     }
     if main_key == "fp64" and "mixed" in res:
         mm = res["mixed"]

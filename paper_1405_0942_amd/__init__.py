@@ -16,7 +16,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librelax.so")
+LIB_PATH = os.environ.get("RELAX_LIB", os.path.join(HERE, "librelax.so"))
 
 RELAX_OK, RELAX_E_ARG, RELAX_E_HIP, RELAX_E_FOLD, RELAX_E_DT, RELAX_E_NAN, RELAX_E_STATE, RELAX_E_SPACE = (
     0, -1, -2, -3, -4, -5, -6, -7)
@@ -286,3 +286,50 @@ class Relaxation:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _relax_function():
+    import torch
+
+    class RelaxK(torch.autograd.Function):
+        """(E_M(x_K), R2(x_K)) after K fixed-dt steps from (x0, B0); backward through the
+        library's reverse-mode sweeps (checkpointed every cfg.checkpoint_every steps).
+
+        Gradients flow to x0 and B0 only (cfg must have record = 1 and adaptive = 0 for an
+        exact gradient; with adaptive = 1 the recorded dt sequence is held fixed)."""
+
+        @staticmethod
+        def forward(ctx, x0, B0, cfg, K):
+            r = Relaxation(cfg, x0.detach().contiguous(), B0.detach().contiguous(), K_record=K)
+            if K > 0:
+                r.step(K, diag=False)
+            d = r.diagnostics()
+            ctx.relax = r
+            dev = x0.device
+            return (torch.tensor(d["E_M"], dtype=torch.float64, device=dev),
+                    torch.tensor(d["R2"], dtype=torch.float64, device=dev))
+
+        @staticmethod
+        def backward(ctx, gE, gR):
+            r = ctx.relax
+            sE = 0.0 if gE is None else float(gE)
+            sR = 0.0 if gR is None else float(gR)
+            gx, gb = r.backward(sE, sR)
+            r.close()
+            ctx.relax = None
+            return gx, gb, None, None
+
+    return RelaxK
+
+
+_RelaxK = None
+
+
+def relax_energy(x0, B0, cfg: relax_config, K: int):
+    """Differentiable (E_M(x_K), R2(x_K)) of K steps from (x0, B0) (torch.autograd.Function)."""
+    global _RelaxK
+    if _RelaxK is None:
+        _RelaxK = _relax_function()
+    if not cfg.record:
+        raise ValueError("relax_energy needs cfg.record = 1")
+    return _RelaxK.apply(x0, B0, cfg, int(K))

@@ -176,6 +176,15 @@ __global__ void to_float_kernel(const double* __restrict__ s, float* __restrict_
     d[i] = (float)s[i];
 }
 
+// component-wise scaling of a [3][N] field in place
+__global__ void prescale_kernel(double* __restrict__ v, long long N, double s0, double s1, double s2) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long long)gridDim.x * blockDim.x) {
+    v[i] *= s0;
+    v[i + N] *= s1;
+    v[i + 2 * N] *= s2;
+  }
+}
+
 // max over nodes of |v|^2 of a [3][N] field (one workgroup; used once at set-up)
 __global__ __launch_bounds__(CT) void max_norm2_kernel(const double* __restrict__ v, long long N,
                                                         double* __restrict__ out) {
@@ -217,6 +226,14 @@ hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_prescale(double* B0, long long N, const double scale[3], hipStream_t st) {
+  long long blocks = (N + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(prescale_kernel, dim3((unsigned)blocks), dim3(256), 0, st, B0, N, scale[0], scale[1], scale[2]);
   return hipGetLastError();
 }
 

@@ -26,7 +26,9 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t ctl, x0, x1, k[5], B0, B0_64, part, lam, ring, out, dtrec, ckpt, adj, total;
+  size_t ctl, x0, x1, k[5], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
+  // reverse mode (record = 1): segment positions and stage vectors, cotangents, seed
+  size_t ctl2, seg_x, seg_k, Fbar, xbar, ybar, B0bar, useed;
   int ckpt_slots;
 };
 
@@ -49,7 +51,14 @@ struct Ctx {
   double* d_out = nullptr;
   double* d_dtrec = nullptr;
   double* d_ckpt = nullptr;
-  char* d_adj = nullptr;
+  Control* d_ctl2 = nullptr;
+  double* d_seg_x = nullptr;
+  double* d_seg_k = nullptr;
+  double* d_Fbar = nullptr;
+  double* d_xbar = nullptr;
+  double* d_ybar = nullptr;
+  double* d_B0bar = nullptr;
+  double* d_useed = nullptr;
   Control* h_ctl = nullptr;  // pinned mirror of the control block
   double* h_ring = nullptr;  // pinned copy of the diagnostics ring
   int status = RELAX_OK;
@@ -95,14 +104,14 @@ bool valid_config(const relax_config* c) {
   return true;
 }
 
-// z-chunk length: enough workgroups to fill 256 CUs several times over, chunks of >= 16
-// planes so the 4 extra stage-input planes per chunk stay a small overhead
+// z-chunk length: about one round of resident workgroups (2 per CU on 256 CUs), chunks of
+// >= 16 planes so the extra stage-input planes at each chunk start stay a small overhead
 int choose_tz(const relax_config* c, int tiles_xy) {
   if (const char* e = std::getenv("RELAX_TZ")) {
     int v = std::atoi(e);
     if (v >= 1) return std::min(v, c->n[2]);
   }
-  const int target_blocks = 2048;
+  const int target_blocks = 512;
   int chunks = std::max(1, (target_blocks + tiles_xy - 1) / tiles_xy);
   int tz = (c->n[2] + chunks - 1) / chunks;
   tz = std::max(tz, 16);
@@ -115,11 +124,14 @@ Geometry make_geometry(const relax_config* c) {
     g.n[a] = c->n[a];
     g.bc[a] = c->bc[a];
     g.h[a] = c->h[a];
-    g.inv2h[a] = 1.0 / (2.0 * c->h[a]);
     g.period[a] = c->n[a] * c->h[a];
   }
   g.N = (long long)c->n[0] * c->n[1] * c->n[2];
   g.dV = c->h[0] * c->h[1] * c->h[2];
+  g.inv8h3 = 1.0 / (8.0 * c->h[0] * c->h[1] * c->h[2]);
+  g.b0scale[0] = 4.0 * c->h[1] * c->h[2];
+  g.b0scale[1] = 4.0 * c->h[2] * c->h[0];
+  g.b0scale[2] = 4.0 * c->h[0] * c->h[1];
   g.tiles[0] = (c->n[0] + TX - 1) / TX;
   g.tiles[1] = (c->n[1] + TY - 1) / TY;
   g.tz = choose_tz(c, g.tiles[0] * g.tiles[1]);
@@ -149,11 +161,21 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   L.ring = take((size_t)RING_CAP * 8 * sizeof(double));
   L.out = take(16 * sizeof(double));
   L.ckpt_slots = 0;
-  L.dtrec = L.ckpt = L.adj = 0;
+  L.dtrec = L.ckpt = 0;
+  L.ctl2 = L.seg_x = L.seg_k = L.Fbar = L.xbar = L.ybar = L.B0bar = L.useed = 0;
   if (c->record && K_record > 0) {
+    const size_t cpe = (size_t)c->checkpoint_every;
     L.dtrec = take((size_t)K_record * sizeof(double));
     L.ckpt_slots = K_record / c->checkpoint_every + 1;
     L.ckpt = take((size_t)L.ckpt_slots * N3 * sizeof(double));
+    L.ctl2 = take(sizeof(Control));
+    L.seg_x = take((cpe + 1) * N3 * sizeof(double));
+    L.seg_k = take(cpe * 5 * N3 * sizeof(double));
+    L.Fbar = take(3 * N3 * sizeof(double));
+    L.xbar = take(N3 * sizeof(double));
+    L.ybar = take(5 * N3 * sizeof(double));
+    L.B0bar = take(N3 * sizeof(double));
+    L.useed = take(N3 * sizeof(double));
   }
   L.total = off;
   return L;
@@ -190,17 +212,19 @@ SweepArgs sweep_args(Ctx* c) {
   a.diag_only = 0;
   a.diag_buf = 0;
   a.u_out = nullptr;
+  a.u_det_scale = 0.0;
   return a;
 }
 
 // FP64 diagnostics sweep of x[buf] into d_out[0..4] = {E, R2, xi, min det, nulls}; host copy.
 // If u_out is not null it also receives the velocity u(x[buf]).
-int diagnostics_sweep(Ctx* c, int buf, double out[5], double* u_out = nullptr) {
+int diagnostics_sweep(Ctx* c, int buf, double out[5], double* u_out = nullptr, double u_det_scale = 0.0) {
   SweepArgs a = sweep_args(c);
   a.B0 = c->d_B0_64;
   a.diag_only = 1;
   a.diag_buf = buf;
   a.u_out = u_out;
+  a.u_det_scale = u_det_scale;
   HIP_TRY(c, launch_diagnostics(a, c->stream));
   HIP_TRY(c, launch_diag_finish(c->d_part, c->g.nblocks, c->g.dV, c->d_out, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->h_ring, c->d_out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -301,6 +325,14 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   if (L.ckpt_slots > 0) {
     c->d_dtrec = reinterpret_cast<double*>(c->base + L.dtrec);
     c->d_ckpt = reinterpret_cast<double*>(c->base + L.ckpt);
+    c->d_ctl2 = reinterpret_cast<Control*>(c->base + L.ctl2);
+    c->d_seg_x = reinterpret_cast<double*>(c->base + L.seg_x);
+    c->d_seg_k = reinterpret_cast<double*>(c->base + L.seg_k);
+    c->d_Fbar = reinterpret_cast<double*>(c->base + L.Fbar);
+    c->d_xbar = reinterpret_cast<double*>(c->base + L.xbar);
+    c->d_ybar = reinterpret_cast<double*>(c->base + L.ybar);
+    c->d_B0bar = reinterpret_cast<double*>(c->base + L.B0bar);
+    c->d_useed = reinterpret_cast<double*>(c->base + L.useed);
   }
   int rc = RELAX_OK;
   auto bail = [&](int code) {
@@ -318,9 +350,12 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   if (hipMemcpyAsync(c->d_x[0], d_x0, N3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->d_B0_64, d_B0, N3 * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return bail(RELAX_E_HIP);
+  // max |B0|^2 of the caller's field (null guard of xi), then B0 -> B0'' = B0 * 4 h_b h_c for
+  // the unscaled-difference form of the sweep
+  if (launch_max_norm2(c->d_B0_64, c->g.N, c->d_out, c->stream) != hipSuccess) return bail(RELAX_E_HIP);
+  if (launch_prescale(c->d_B0_64, c->g.N, c->g.b0scale, c->stream) != hipSuccess) return bail(RELAX_E_HIP);
   if (c->mixed && launch_to_float(c->d_B0_64, static_cast<float*>(c->d_B0), (long long)N3, c->stream) != hipSuccess)
     return bail(RELAX_E_HIP);
-  if (launch_max_norm2(c->d_B0_64, c->g.N, c->d_out, c->stream) != hipSuccess) return bail(RELAX_E_HIP);
   if (hipMemcpyAsync(c->h_ring, c->d_out, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(RELAX_E_HIP);
@@ -434,7 +469,87 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
   Ctx* c = static_cast<Ctx*>(ctx);
   if (!c || !d_grad_x0 || !d_grad_B0 || !std::isfinite(seed_EM) || !std::isfinite(seed_R2)) return RELAX_E_ARG;
   if (c->status != RELAX_OK) return RELAX_E_STATE;
-  return fail(c, RELAX_E_STATE, "relax_backward: no recorded fixed-dt trajectory");
+  if (c->mixed) return fail(c, RELAX_E_ARG, "relax_backward: needs an FP64 context");
+  if (c->L.ckpt_slots == 0) return fail(c, RELAX_E_STATE, "relax_backward: context created without record");
+  if (seed_R2 != 0.0 && c->cfg.gamma == 0.0) return fail(c, RELAX_E_ARG, "relax_backward: R2 seed needs gamma != 0");
+  int rc = sync_ctl(c);
+  if (rc) return rc;
+  const long long K = c->h_ctl->steps_total;
+  if (K > c->K_record) return fail(c, RELAX_E_STATE, "relax_backward: more steps taken than K_record");
+  const long long N = c->g.N;
+  const size_t N3 = 3 * (size_t)N;
+  const int cpe = c->cfg.checkpoint_every;
+  hipStream_t st = c->stream;
+
+  AdjArgs a{};
+  a.g = c->g;
+  a.B0 = c->d_B0_64;
+  a.Fbar = c->d_Fbar;
+  a.B0bar = c->d_B0bar;
+  a.gamma = c->cfg.gamma;
+  a.seed_EM = seed_EM;
+  a.seed_R2 = seed_R2;
+  a.xbar = c->d_xbar;
+  for (int t = 2; t <= 6; t++) a.ybar[t] = c->d_ybar + (size_t)(t - 2) * N3;
+  HIP_TRY(c, launch_fill(c->d_B0bar, (long long)N3, 0.0, st));
+
+  // seed: cotangents of E_M(x_K) and R2(x_K)
+  a.useed = nullptr;
+  if (seed_R2 != 0.0) {
+    double d[5];
+    const double gm = c->cfg.gamma;
+    if ((rc = diagnostics_sweep(c, c->cur, d, c->d_useed, c->g.dV * seed_R2 / (gm * gm))) != RELAX_OK) return rc;
+    a.useed = c->d_useed;
+  }
+  a.x = c->d_x[c->cur];
+  HIP_TRY(c, launch_adj_field(1, true, a, st));
+  a.xbar_out = c->d_xbar;
+  HIP_TRY(c, launch_adj_gather(a, 2, st));
+  a.useed = nullptr;
+
+  // reverse over the recorded steps, one checkpoint segment at a time
+  HIP_TRY(c, hipMemcpyAsync(c->d_ctl2, c->d_ctl, sizeof(Control), hipMemcpyDeviceToDevice, st));
+  SweepArgs fw = sweep_args(c);
+  fw.ctl = c->d_ctl2;
+  fw.B0 = c->d_B0_64;
+  fw.ckpt = nullptr;
+  fw.ckpt_slots = 0;
+  const long long nseg = (K + cpe - 1) / cpe;
+  for (long long seg = nseg - 1; seg >= 0; seg--) {
+    const long long s0 = seg * cpe, s1 = std::min<long long>(s0 + cpe, K);
+    const int len = (int)(s1 - s0);
+    HIP_TRY(c, hipMemcpyAsync(c->d_seg_x, c->d_ckpt + (size_t)seg * N3, N3 * sizeof(double),
+                              hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < len; j++) {  // forward recompute, keeping x_n and k_1..k_5 of every step
+      HIP_TRY(c, launch_seg_step(c->d_ctl2, c->d_dtrec, s0 + j, st));
+      fw.x[0] = c->d_seg_x + (size_t)j * N3;
+      fw.x[1] = c->d_seg_x + (size_t)(j + 1) * N3;
+      fw.xout[0] = c->d_seg_x + (size_t)j * N3;
+      fw.xout[1] = c->d_seg_x + (size_t)(j + 1) * N3;
+      for (int s = 0; s < 5; s++) fw.k[s] = c->d_seg_k + ((size_t)j * 5 + s) * N3;
+      for (int s = 1; s <= 6; s++) HIP_TRY(c, launch_stage(s, false, fw, st));
+    }
+    for (int j = len - 1; j >= 0; j--) {
+      a.x = c->d_seg_x + (size_t)j * N3;
+      for (int s = 0; s < 5; s++) a.k[s] = c->d_seg_k + ((size_t)j * 5 + s) * N3;
+      a.dt = c->d_dtrec + s0 + j;
+      for (int s = 6; s >= 1; s--) {
+        HIP_TRY(c, launch_adj_field(s, false, a, st));
+        if (s >= 2) {
+          a.ybar_out = c->d_ybar + (size_t)(s - 2) * N3;
+          HIP_TRY(c, launch_adj_gather(a, 0, st));
+        } else {
+          a.xbar_out = c->d_xbar;
+          HIP_TRY(c, launch_adj_gather(a, 1, st));
+        }
+      }
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(d_grad_x0, c->d_xbar, N3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(d_grad_B0, c->d_B0bar, N3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, launch_prescale(d_grad_B0, N, c->g.b0scale, st));  // d/dB0 = 4 h_b h_c d/dB0''
+  HIP_TRY(c, hipStreamSynchronize(st));
+  return RELAX_OK;
 }
 
 int relax_get_state(void* ctx, double* d_x_out, double* t, double* dt) {

@@ -27,10 +27,11 @@ struct Geometry {
   int n[3];          // nodes along x, y, z
   int bc[3];         // BC_LINE_TIED / BC_PERIODIC per axis
   double h[3];       // reference spacing
-  double inv2h[3];   // 1 / (2 h)
   double period[3];  // n h (used on periodic axes)
   long long N;       // number of nodes
   double dV;         // hx hy hz
+  double inv8h3;     // 1 / (8 hx hy hz): det F = det F' * inv8h3 for the unscaled differences F'
+  double b0scale[3]; // 4 h_b h_c: B0'' = B0 * b0scale (component-wise), see stage.hip
   int tiles[3];      // tiles along x, along y, z-chunks
   int tz;            // z-chunk length
   int nblocks;       // tiles[0] * tiles[1] * tiles[2]
@@ -73,6 +74,24 @@ struct SweepArgs {
   int diag_only;       // 1: diagnostics sweep of x[diag_buf] (no gating, no k written)
   int diag_buf;
   double* u_out;       // diagnostics sweep only: if not null, receives u(x) [3][N] (FP64)
+  double u_det_scale;  // diagnostics sweep only: if not 0, u_out holds u * det F * u_det_scale
+};
+
+// Arguments of the reverse-mode sweeps (adjoint.hip).  FP64 throughout.
+struct AdjArgs {
+  Geometry g;
+  const double* x;        // x_n of the step (or x_K for the seed sweep)
+  const double* k[5];     // k_1..k_5 of the step
+  const double* dt;       // device pointer to the step's dt
+  const double* B0;       // B0'' (prescaled, FP64)
+  const double* xbar;     // cotangent of x_{n+1}
+  const double* ybar[7];  // ybar_t for t = 2..6 (index t)
+  const double* useed;    // seed sweep: cotangent of u (may be null)
+  double* Fbar;           // [9][N] cotangent of F' (row-major 3x3 per node, component-major)
+  double* B0bar;          // [3][N] accumulated cotangent of B0''
+  double* ybar_out;       // gather mode 0 output
+  double* xbar_out;       // gather modes 1, 2 output
+  double gamma, seed_EM, seed_R2;
 };
 
 // Cash-Karp RK5(4) coefficients (Cash & Karp 1990): stage rows a_sj, 5th and 4th order
@@ -101,6 +120,11 @@ hipError_t launch_control(Control* ctl, const double* part, const double* lam_pa
 hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out5, hipStream_t st);
 hipError_t launch_begin_chunk(Control* ctl, int target, hipStream_t st);
 hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t st);
+hipError_t launch_prescale(double* B0, long long N, const double scale[3], hipStream_t st);
+hipError_t launch_adj_field(int s, bool seed, const AdjArgs& a, hipStream_t st);
+hipError_t launch_adj_gather(const AdjArgs& a, int mode, hipStream_t st);
+hipError_t launch_fill(double* v, long long n, double val, hipStream_t st);
+hipError_t launch_seg_step(Control* c2, const double* dt_record, long long n, hipStream_t st);
 hipError_t launch_max_norm2(const double* v, long long N, double* out, hipStream_t st);
 
 }  // namespace relax
