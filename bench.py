@@ -29,10 +29,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point updates/s (FP64 vs FP32-mixed) + % HBM roofline at 256^3"
 
-# algorithmic HBM bytes per node of each stage sweep (read x_n, k_1..k_{s-1}, B0; write k_s;
-# stage 6 writes x_{n+1} instead of k_6) -- FP64 and FP32-mixed (x in FP64, k and B0 in FP32)
-BYTES_FP64 = [72, 96, 120, 144, 168, 192]
-BYTES_MIXED = [48, 60, 72, 84, 96, 120]
+# algorithmic HBM bytes per node of each stage sweep, FP64 and FP32-mixed (x_n and the stage
+# inputs y_s in FP64; k_j and B0 in FP32 in mixed mode):
+#   stage 1: x_n, B0 -> k_1
+#   stage 2: x_n, k_1, B0, k_1 at the node -> k_2, y_3
+#   stage s = 3..5: y_s, B0, k_1..k_{s-1} at the node -> k_s, y_{s+1}
+#   stage 6: y_6, B0, x_n, k_1, k_3, k_4, k_5 at the node -> x_{n+1}
+BYTES_FP64 = [72, 144, 144, 168, 192, 192]
+BYTES_MIXED = [48, 96, 96, 108, 120, 132]
 
 
 def log(msg):
@@ -79,6 +83,8 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
     kernels["control"] = {"total_ms": prof["control"][0], "launches": prof["control"][1]}
     dom = max((k for k in kernels if "avg_ms" in kernels[k]), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     achieved = kernels[dom]["GB/s"]
+    tag = "fp64" if precision == R.RELAX_FP64 else "fp32-mixed"
+    traffic = measured_traffic(int(dom[-1]), tag, w.name.replace("^3", ""))
     step_bytes = sum(bytes_node) * N
     out.update(
         value=N * steps / wall,
@@ -93,11 +99,22 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
         fp64_final_xi=fin["xi"],
         step_GBs=step_bytes * steps / wall / 1e9,
         kernels=kernels,
-        roofline={"bound": "hbm", "kernel": f"stage_kernel<{dom[-1]}> ({'fp64' if precision == 0 else 'fp32-mixed'})",
+        roofline={"bound": "hbm", "kernel": f"stage_kernel<{dom[-1]}> ({tag})",
                   "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                  "traffic": None},
+                  "traffic": traffic, "algorithmic_bytes": bytes_node[int(dom[-1]) - 1] * N},
     )
     return out
+
+
+def measured_traffic(stage, tag, workload):
+    """HBM bytes per launch of stage_kernel<stage> from the committed FETCH_SIZE / WRITE_SIZE
+    summary of this workload, or None when there is none or the kernel source changed since."""
+    from paper_1405_0942_amd import profiling
+    rec = profiling.read_traffic(os.path.join(ROOT, "profiles", f"stage_kernel_{workload}_{tag}_traffic.txt"))
+    if rec is None or rec.get("source_sha256") != profiling.kernel_source_hash():
+        return None
+    v = rec.get(f"stage{stage}_bytes_per_launch")
+    return float(v) if v is not None else None
 
 
 def copy_bandwidth(torch, mib=1024, reps=5):

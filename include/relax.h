@@ -50,7 +50,7 @@ enum { RELAX_LINE_TIED = 0, RELAX_PERIODIC = 1 };
 enum { RELAX_FP64 = 0, RELAX_FP32_MIXED = 1 };
 
 typedef struct {
-  int n[3];             /* nodes along x, y, z; each >= 4 */
+  int n[3];             /* nodes along x, y, z; each >= 4, n[0] * n[1] < 2^28 */
   double h[3];          /* reference spacing dX, dY, dZ (> 0).  Periodic period P_a = n_a h_a */
   int bc[3];            /* per axis RELAX_LINE_TIED or RELAX_PERIODIC (Sec. 2.5) */
   int precision;        /* RELAX_FP64, or RELAX_FP32_MIXED: stage vectors, B0 copy and the

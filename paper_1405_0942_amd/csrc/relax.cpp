@@ -26,7 +26,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t ctl, x0, x1, k[5], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
+  size_t ctl, x0, x1, k[5], y[2], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
   // reverse mode (record = 1): segment positions and stage vectors, cotangents, seed
   size_t ctl2, seg_x, seg_k, Fbar, xbar, ybar, B0bar, useed;
   int ckpt_slots;
@@ -43,6 +43,7 @@ struct Ctx {
   Control* d_ctl = nullptr;
   double* d_x[2] = {nullptr, nullptr};
   void* d_k[5] = {};
+  double* d_y[2] = {nullptr, nullptr};
   void* d_B0 = nullptr;
   double* d_B0_64 = nullptr;
   double* d_part = nullptr;
@@ -94,7 +95,7 @@ bool valid_config(const relax_config* c) {
     if (c->n[a] < 4 || !(c->h[a] > 0.0) || !std::isfinite(c->h[a])) return false;
     if (c->bc[a] != RELAX_LINE_TIED && c->bc[a] != RELAX_PERIODIC) return false;
   }
-  if ((long long)c->n[0] * c->n[1] > (1LL << 30) || (long long)c->n[0] * c->n[1] * c->n[2] > (1LL << 40)) return false;
+  if ((long long)c->n[0] * c->n[1] >= (1LL << 28) || (long long)c->n[0] * c->n[1] * c->n[2] > (1LL << 40)) return false;
   if (c->precision != RELAX_FP64 && c->precision != RELAX_FP32_MIXED) return false;
   if (!std::isfinite(c->gamma) || !(c->dt0 > 0.0) || !std::isfinite(c->dt0)) return false;
   if (!(c->dt_min >= 0.0) || !(c->tol > 0.0) || !(c->xi_null_tau >= 0.0)) return false;
@@ -154,6 +155,7 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   L.x0 = take(N3 * sizeof(double));
   L.x1 = take(N3 * sizeof(double));
   for (int s = 0; s < 5; s++) L.k[s] = take(N3 * ts);
+  for (int t = 0; t < 2; t++) L.y[t] = take(N3 * sizeof(double));
   L.B0_64 = take(N3 * sizeof(double));
   L.B0 = (c->precision == RELAX_FP32_MIXED) ? take(N3 * sizeof(float)) : L.B0_64;
   L.part = take((size_t)g.nblocks * NPART * sizeof(double));
@@ -203,6 +205,8 @@ SweepArgs sweep_args(Ctx* c) {
   a.xout[1] = c->d_x[1];
   for (int s = 0; s < 5; s++) a.k[s] = c->d_k[s];
   a.k[5] = nullptr;
+  a.y[0] = c->d_y[0];
+  a.y[1] = c->d_y[1];
   a.B0 = c->d_B0;
   a.ctl = c->d_ctl;
   a.part = c->d_part;
@@ -316,6 +320,7 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   c->d_x[0] = reinterpret_cast<double*>(c->base + L.x0);
   c->d_x[1] = reinterpret_cast<double*>(c->base + L.x1);
   for (int s = 0; s < 5; s++) c->d_k[s] = c->base + L.k[s];
+  for (int t = 0; t < 2; t++) c->d_y[t] = reinterpret_cast<double*>(c->base + L.y[t]);
   c->d_B0_64 = reinterpret_cast<double*>(c->base + L.B0_64);
   c->d_B0 = c->base + L.B0;
   c->d_part = reinterpret_cast<double*>(c->base + L.part);

@@ -65,6 +65,7 @@ struct SweepArgs {
   const double* x[2];  // position buffers (x_n is x[ctl->cur])
   double* xout[2];     // same buffers, writable (stage 6 writes x[1 - cur])
   void* k[6];          // stage vectors k1..k5 (double, or float in mixed mode)
+  double* y[2];        // stage inputs y_3..y_6 (y_t in y[t % 2]), written by stages 2..5
   const void* B0;      // initial field (double, or float in mixed mode)
   Control* ctl;
   double* part;        // [nblocks][NPART] reduction partials of stage 1 / diagnostics

@@ -24,20 +24,25 @@
 // paper's 3x3 system is (cof F)^T J = c, solved by J = F c / det F; with F = F' diag(1/2h)
 // and G = G' diag(1/2h) every spacing factor cancels.
 //
+// Stage inputs.  Stage 1 differentiates x_n; stage 2 assembles y_2 = x_n + dt a_21 k_1
+// from x_n and k_1 on the fly.  Stages 2..5 also write the NEXT stage's input pointwise,
+//     y_{s+1} = y_s + dt sum_{j<s} (a_{s+1,j} - a_{s,j}) k_j + dt a_{s+1,s} k_s,
+// so stages 3..6 stencil one vector (y_s) instead of x_n and every earlier k_j with
+// halos; the k_j they still need are read at the output node only.  A retried step
+// (smaller dt, same x_n and k_1) starts again at stage 2, which rebuilds y_2 and y_3.
+//
 // Data flow: a workgroup owns a 64 x 4 (x, y) tile and marches up a z-chunk.  Each plane
-// of the stage input y (tile + 2-node halo, FP64) is assembled from x_n and the k_j into an
-// LDS ring of three planes; F', det F' and B are formed on the tile + 1-node halo into an
-// LDS ring of three B planes; the current, force and velocity are formed on the tile one
-// plane behind.  The global loads of the next plane are issued before the current plane
-// is computed and committed to LDS after it.
+// of the stage input (tile + 2-node halo, FP64) goes into an LDS ring of three planes;
+// F', det F' and B are formed on the tile + 1-node halo into an LDS ring of two B planes
+// (the z difference of B at the tile node uses the node's own B of the neighbouring
+// planes, kept in registers); the current, force and velocity are formed on the tile one
+// plane behind.  Every global access is a buffer instruction whose masked-off lanes carry
+// an offset past the record count (loads return 0, stores are dropped), so the march has
+// no divergent branch around a memory instruction: each load is issued one plane step
+// before its use, in the same order on every step, and waited for by exact counts.
 #include <type_traits>
 
 #include "relax_device.h"
-
-// k vectors of an FP64 stage input loaded before the field computation (the rest after it)
-#ifndef RELAX_FP64_PHASE_A
-#define RELAX_FP64_PHASE_A 5
-#endif
 
 namespace relax {
 namespace {
@@ -63,6 +68,33 @@ __device__ __forceinline__ AxisIdx resolve(int v, int n, int bc) {
     r.ok = (v >= 0 && v < n);
   }
   return r;
+}
+
+// ---- buffer access --------------------------------------------------------------------------
+// Element index of a masked-off lane: scaled by the element size it lands at or past the
+// record count of every plane (a plane holds fewer than 2^28 nodes).
+constexpr unsigned IE = 1u << 28;
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer resource, gfx9 encoding
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// resource for one component plane [base, base + nxy)
+template <typename V>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const V* base, unsigned nxy) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<V*>(base), 0, (int)(nxy * sizeof(V)), RSRC_WORD3);
+}
+template <typename V>
+__device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, unsigned e) {
+  if constexpr (sizeof(V) == 8)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, 0));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e * 4u), 0, 0));
+}
+template <typename V>
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned e, V v) {
+  if constexpr (sizeof(V) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(e * 4u), 0, 0);
 }
 
 // logical tile of this workgroup; consecutive logical tiles share an XCD (the hardware
@@ -108,14 +140,23 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
+// the k_j a stage reads at its output node: k_1..k_{s-1} for stages 2..5 (for y_{s+1});
+// k_1, k_3, k_4, k_5 for stage 6 (the weights of k_2 in x5 and in x5 - x4 vanish)
+template <int S>
+__device__ __forceinline__ constexpr int point_k(int j) {
+  return (S == 6) ? (j == 0 ? 0 : j + 1) : j;
+}
+
 // S: stage 1..6.  MIXED: k and B0 in FP32 and the stencil past F' in FP32.  XYP: x and y
-// both periodic (no line-tied rows or range checks in x and y).
+// both periodic (no line-tied rows in x and y).
 template <int S, bool MIXED, bool XYP>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(SweepArgs a) {
   using T = typename std::conditional<MIXED, float, double>::type;
   constexpr bool STAGE1 = (S == 1);
   constexpr bool LAST = (S == 6);
-  constexpr int NK = (S > 1) ? S - 1 : 1;                     // k vectors in the stage input
+  constexpr bool WK = (S == 2);                                // the window carries k_1 too
+  constexpr int NPK = STAGE1 ? 0 : (LAST ? 4 : S - 1);        // k_j read at the output node
+  constexpr int NPKA = NPK > 0 ? NPK : 1;
   constexpr int NP2 = (RY2 * RX2 + NTHREADS - 1) / NTHREADS;  // stage-input points per thread
   constexpr int NP1 = (RY1 * RX1 + NTHREADS - 1) / NTHREADS;  // field points per thread
 
@@ -142,10 +183,15 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   }
   const double gamma = ctl->gamma;
   const double tau_B2 = ctl->tau_B2;
-  // dt a_sj folded into one coefficient per k_j
-  double cka[NK];
+  // y_2 = x + c21 k_1 (stage-2 window); y_{s+1} = y_s + sum_j cy[j] k_j + cys k_s (output)
+  const double c21 = dt * CK::a[1][0];
+  double cy[NPKA] = {};
+  double cys = 0.0;
+  if constexpr (S >= 2 && S <= 5) {
 #pragma unroll
-  for (int j = 0; j < NK; j++) cka[j] = (S > 1) ? dt * CK::a[S - 1][j] : 0.0;
+    for (int j = 0; j < NPK; j++) cy[j] = dt * (CK::a[S][j] - CK::a[S - 1][j]);
+    cys = dt * CK::a[S][S - 1];
+  }
 
   const Geometry& g = a.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -154,6 +200,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   const int bcy = XYP ? BC_PERIODIC : g.bc[1];
   const int bcz = g.bc[2];
   const double inv8h3 = g.inv8h3;
+  const unsigned nxy = (unsigned)nx * (unsigned)ny;
 
   const int lb = logical_block(blockIdx.x, g.nblocks);
   const int tile_x = lb % g.tiles[0];
@@ -167,27 +214,35 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   const int tx = tid % TX, ty = tid / TX;
 
   __shared__ double ys[3][3][RY2 * RX2];  // stage input, tile + 2-node halo, ring of 3 planes
-  __shared__ T bs[3][3][RY1 * RX1];       // pulled-back field, tile + 1-node halo, ring of 3
+  __shared__ T bs[2][3][RY1 * RX1];       // pulled-back field, tile + 1-node halo, 2 planes
   __shared__ double red[NTHREADS / 64][NPART];
 
   const double* __restrict__ xn = a.x[cur];
+  const double* __restrict__ wsrc = (S <= 2) ? xn : a.y[S & 1];  // the stencilled vector
+  const T* __restrict__ k1p = static_cast<const T*>(a.k[0]);
   const T* __restrict__ b0p = static_cast<const T*>(a.B0);
-  const long long nxy = (long long)nx * ny;
+
+  // plane index of a load (line-tied z: clamped; such planes are loaded but never used)
+  auto zload = [&](int pz) {
+    if (bcz == BC_PERIODIC) return resolve(pz, nz, bcz).i;
+    return min(max(pz, 0), nz - 1);
+  };
 
   // ---- per-thread index tables: the (x, y) part of every address is the same on all planes
-  int w2xy[NP2];  // stage-input window point -> flat (x, y) index, -1 off the grid
-  int w2w[NP2];   // its periodic wraps: x in the low 16 bits, y in the high 16 bits (signed)
+  unsigned w2e[NP2];  // stage-input window point -> flat (x, y) index, IE off the grid
+  int w2w[NP2];       // its periodic wraps: x in the low 16 bits, y in the high 16 bits (signed)
 #pragma unroll
   for (int r = 0; r < NP2; r++) {
     const int e = tid + r * NTHREADS;
     const int row = e / RX2, col = e - row * RX2;
     const AxisIdx rx = resolve(i0 + col - 2, nx, bcx);
     const AxisIdx ry = resolve(j0 + row - 2, ny, bcy);
-    w2xy[r] = (e < RY2 * RX2 && rx.ok && ry.ok) ? ry.i * nx + rx.i : -1;
+    w2e[r] = (e < RY2 * RX2 && rx.ok && ry.ok) ? (unsigned)(ry.i * nx + rx.i) : IE;
     w2w[r] = (ry.w << 16) + (rx.w & 0xffff);
   }
-  // field point e: e < NTHREADS is the tile point of thread e; the rest is the halo ring
-  int f1xy[NP1], f1r[NP1], f1c[NP1];
+  // field point e: e < NTHREADS is the tile node of thread e; the rest is the halo ring
+  unsigned f1e[NP1];
+  int f1r[NP1], f1c[NP1];
 #pragma unroll
   for (int r = 0; r < NP1; r++) {
     const int e = tid + r * NTHREADS;
@@ -210,111 +265,86 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       }
     }
     const AxisIdx rx = resolve(i0 + c1 - 1, nx, bcx), ry = resolve(j0 + r1 - 1, ny, bcy);
-    f1xy[r] = (e < RY1 * RX1 && rx.ok && ry.ok) ? ry.i * nx + rx.i : -1;
+    f1e[r] = (e < RY1 * RX1 && rx.ok && ry.ok) ? (unsigned)(ry.i * nx + rx.i) : IE;
     f1r[r] = (e < RY1 * RX1) ? r1 : -1;
     f1c[r] = c1;
   }
 
-  // ---- stage-input plane: global loads into registers (issue), then y -> LDS (commit) ----
-  // Phase A (x_n and the first NA k_j) is issued before the field computation of the
-  // current plane; with FP64 stage vectors the remaining NB k_j (phase B) are issued after
-  // phase A has been folded into a partial sum, which bounds the registers held in flight.
-  constexpr int NA = MIXED ? NK : (NK < RELAX_FP64_PHASE_A ? NK : RELAX_FP64_PHASE_A);
-  constexpr int NB = (S > 1) ? (S - 1) - NA : 0;
-  constexpr int NBA = NB > 0 ? NB : 1;
-  double px[NP2][3];
-  T pk[NK][NP2][3];
-  T pkb[NBA][NP2][3];
-  double yacc[NP2][3];
-  auto issue_a = [&](int pz) {
-    const long long zo = resolve(pz, nz, bcz).i * nxy;
+  // tile node owned by this thread
+  const int gi_t = i0 + tx, gj_t = j0 + ty;
+  const bool tile_ok = (gi_t < nx) && (gj_t < ny);
+  const unsigned out_e = tile_ok ? (unsigned)(gj_t * nx + gi_t) : IE;
+  const bool face_xy = !XYP && ((bcx == BC_LINE_TIED && (gi_t == 0 || gi_t == nx - 1)) ||
+                                (bcy == BC_LINE_TIED && (gj_t == 0 || gj_t == ny - 1)));
+
+  // ---- loads of one plane, issued one plane step ahead of their use -------------------------
+  double wx[NP2][3];       // stage-input window (x_n, or y_s)
+  T wk[WK ? NP2 : 1][3];   // stage 2: k_1 on the window
+  T b0r[NP1][3];           // B0'' at the field points
+  double px[LAST ? 3 : 1]; // stage 6: x_n at the output node
+  T pk[NPKA][3];           // k_j at the output node
+  auto load_window = [&](int pz) {
+    const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
-    for (int r = 0; r < NP2; r++) {
-      if (w2xy[r] >= 0) {
-        const unsigned o = (unsigned)w2xy[r];
+    for (int m = 0; m < 3; m++) {
+      const auto rs = plane_rsrc(wsrc + m * N + zo, nxy);
 #pragma unroll
-        for (int m = 0; m < 3; m++) px[r][m] = (xn + zo + m * N)[o];
-        if constexpr (S > 1) {
-#pragma unroll
-          for (int j = 0; j < NA; j++) {
-            const T* __restrict__ kj = static_cast<const T*>(a.k[j]) + zo;
-#pragma unroll
-            for (int m = 0; m < 3; m++) pk[j][r][m] = (kj + m * N)[o];
-          }
-        }
-      }
+      for (int r = 0; r < NP2; r++) wx[r][m] = bload<double>(rs, w2e[r]);
     }
-  };
-  auto fold_a = [&]() {
-#pragma unroll
-    for (int r = 0; r < NP2; r++)
+    if constexpr (WK) {
 #pragma unroll
       for (int m = 0; m < 3; m++) {
-        double y = px[r][m];
-        if constexpr (S > 1) {
+        const auto rs = plane_rsrc(k1p + m * N + zo, nxy);
 #pragma unroll
-          for (int j = 0; j < NA; j++) y = fma(cka[j], (double)pk[j][r][m], y);
-        }
-        yacc[r][m] = y;
-      }
-  };
-  auto issue_b = [&](int pz) {
-    if constexpr (NB > 0) {
-      const long long zo = resolve(pz, nz, bcz).i * nxy;
-#pragma unroll
-      for (int r = 0; r < NP2; r++) {
-        if (w2xy[r] >= 0) {
-          const unsigned o = (unsigned)w2xy[r];
-#pragma unroll
-          for (int j = 0; j < NB; j++) {
-            const T* __restrict__ kj = static_cast<const T*>(a.k[NA + j]) + zo;
-#pragma unroll
-            for (int m = 0; m < 3; m++) pkb[j][r][m] = (kj + m * N)[o];
-          }
-        }
+        for (int r = 0; r < NP2; r++) wk[r][m] = bload<T>(rs, w2e[r]);
       }
     }
   };
-  auto commit_plane = [&](int pz) {
+  auto commit_window = [&](int pz) {
     const AxisIdx rz = resolve(pz, nz, bcz);
     const int slot = mod3(pz);
     const double shz = rz.w * g.period[2];
-    if constexpr (NB == 0) fold_a();
 #pragma unroll
     for (int r = 0; r < NP2; r++) {
       const int e = tid + r * NTHREADS;
+      const bool ok = (w2e[r] != IE);
+      double v[3];
+#pragma unroll
+      for (int m = 0; m < 3; m++) {
+        double y = wx[r][m];
+        if constexpr (WK) y = fma(c21, (double)wk[r][m], y);
+        v[m] = y;
+      }
+      v[0] += (double)(short)(w2w[r] & 0xffff) * g.period[0];
+      v[1] += (double)(w2w[r] >> 16) * g.period[1];
+      v[2] += shz;
       if (e < RY2 * RX2) {
-        double v[3] = {0.0, 0.0, 0.0};
-        if (w2xy[r] >= 0) {
 #pragma unroll
-          for (int m = 0; m < 3; m++) {
-            double y = yacc[r][m];
-            if constexpr (NB > 0) {
-#pragma unroll
-              for (int j = 0; j < NB; j++) y = fma(cka[NA + j], (double)pkb[j][r][m], y);
-            }
-            v[m] = y;
-          }
-          v[0] += (double)(short)(w2w[r] & 0xffff) * g.period[0];
-          v[1] += (double)(w2w[r] >> 16) * g.period[1];
-          v[2] += shz;
-        }
-#pragma unroll
-        for (int m = 0; m < 3; m++) ys[slot][m][e] = v[m];
+        for (int m = 0; m < 3; m++) ys[slot][m][e] = ok ? v[m] : 0.0;
       }
     }
   };
-  auto issue_b0 = [&](int p, T (&dst)[NP1][3]) {
-    const long long zo = resolve(p, nz, bcz).i * nxy;
+  auto load_b0 = [&](int pz) {
+    const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
-    for (int r = 0; r < NP1; r++) {
-      if (f1xy[r] >= 0) {
-        const unsigned o = (unsigned)f1xy[r];
+    for (int m = 0; m < 3; m++) {
+      const auto rs = plane_rsrc(b0p + m * N + zo, nxy);
 #pragma unroll
-        for (int m = 0; m < 3; m++) dst[r][m] = (b0p + zo + m * N)[o];
-      } else {
+      for (int r = 0; r < NP1; r++) b0r[r][m] = bload<T>(rs, f1e[r]);
+    }
+  };
+  auto load_point = [&](int pz) {
+    if constexpr (NPK > 0) {
+      const long long zo = (long long)zload(pz) * nxy;
+      if constexpr (LAST) {
 #pragma unroll
-        for (int m = 0; m < 3; m++) dst[r][m] = T(0);
+        for (int m = 0; m < 3; m++) px[m] = bload<double>(plane_rsrc(xn + m * N + zo, nxy), out_e);
+      }
+#pragma unroll
+      for (int j = 0; j < NPK; j++) {
+        const T* kj = static_cast<const T*>(a.k[point_k<S>(j)]);
+#pragma unroll
+        for (int m = 0; m < 3; m++) pk[j][m] = bload<T>(plane_rsrc(kj + m * N + zo, nxy), out_e);
       }
     }
   };
@@ -341,24 +371,8 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     }
   };
   auto jacobian = [&](int r, int c, int p, int gi, int gj, double F[3][3]) {
+    jac_xy(r, c, p, gi, gj, F);
     const int o = r * RX2 + c;
-    const int sp = mod3(p);
-#pragma unroll
-    for (int m = 0; m < 3; m++) {
-      const double* yc = ys[sp][m];
-      if (XYP || bcx == BC_PERIODIC || (gi > 0 && gi < nx - 1))
-        F[m][0] = yc[o + 1] - yc[o - 1];
-      else if (gi == 0)
-        F[m][0] = -3.0 * yc[o] + 4.0 * yc[o + 1] - yc[o + 2];
-      else
-        F[m][0] = 3.0 * yc[o] - 4.0 * yc[o - 1] + yc[o - 2];
-      if (XYP || bcy == BC_PERIODIC || (gj > 0 && gj < ny - 1))
-        F[m][1] = yc[o + RX2] - yc[o - RX2];
-      else if (gj == 0)
-        F[m][1] = -3.0 * yc[o] + 4.0 * yc[o + RX2] - yc[o + 2 * RX2];
-      else
-        F[m][1] = 3.0 * yc[o] - 4.0 * yc[o - RX2] + yc[o - 2 * RX2];
-    }
     if (bcz == BC_PERIODIC || (p > 0 && p < nz - 1)) {
       const int sa = mod3(p + 1), sb = mod3(p - 1);
 #pragma unroll
@@ -380,40 +394,70 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   auto need_hi = [&](int p) { return perz ? p + 1 : (p == 0 ? 2 : (p == nz - 1 ? p : p + 1)); };
   auto need_lo = [&](int p) { return perz ? p - 1 : (p == 0 ? 0 : (p == nz - 1 ? p - 2 : p - 1)); };
 
-  // tile point owned by this thread
-  const int gi_t = i0 + tx, gj_t = j0 + ty;
-  const bool tile_ok = (gi_t < nx) && (gj_t < ny);
-  const bool face_xy = !XYP && ((bcx == BC_LINE_TIED && (gi_t == 0 || gi_t == nx - 1)) ||
-                                (bcy == BC_LINE_TIED && (gj_t == 0 || gj_t == ny - 1)));
-
   // reductions
   double acc_E = 0.0, acc_R2 = 0.0, acc_xi = 0.0, acc_min = INFINITY, acc_null = 0.0, acc_lam = 0.0;
 
-  // one plane step: field B(p) on the tile + halo (tile point's F' -> Fo, 1/det F' -> rDo,
-  // det F -> Do), then u at plane q = p - 1 from Fi / rDi / Di (the previous plane's)
-  auto plane = [&](int p, const double (&Fzi)[3], double rDi, double Di, double (&Fzo)[3], double& rDo,
-                   double& Do, T (&b0use)[NP1][3]) {
-    // the per-lane offsets are made opaque here so that the compiler recomputes addresses
-    // per plane instead of keeping one hoisted 64-bit address per array, component and slot
+  // ---- stores of one output plane (every lane issues them; masked-off lanes are dropped) ----
+  // stage 1: k_1 (or u, in a diagnostics sweep that asks for it) and the checkpoint copy of
+  // x_n; stages 2..5: k_s and y_{s+1}; stage 6: x_{n+1}
+  T so_k[3] = {T(0), T(0), T(0)};
+  double so_y[3] = {0.0, 0.0, 0.0};
+  auto store_plane = [&](int qz, bool on) {
+    const long long zo = (long long)zload(qz) * nxy;
+    if constexpr (STAGE1) {
+      const bool to_u = !MIXED && diag_only && a.u_out != nullptr;
+      const unsigned ek = (on && (!diag_only || to_u)) ? out_e : IE;
+      const unsigned ec = (on && record_ck) ? out_e : IE;
+      T* dk = to_u ? reinterpret_cast<T*>(a.u_out) : static_cast<T*>(a.k[0]);
+      double* dc = record_ck ? a.ckpt + ck_slot * 3 * N : a.xout[0];
 #pragma unroll
-    for (int r = 0; r < NP2; r++) asm volatile("" : "+v"(w2xy[r]));
+      for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), ek, so_k[m]);
 #pragma unroll
-    for (int r = 0; r < NP1; r++) asm volatile("" : "+v"(f1xy[r]));
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dc + m * N + zo, nxy), ec, so_y[m]);
+    } else if constexpr (!LAST) {
+      const unsigned eo = on ? out_e : IE;
+      T* dk = static_cast<T*>(a.k[S - 1]);
+      double* dy = a.y[(S + 1) & 1];
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), eo, so_k[m]);
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dy + m * N + zo, nxy), eo, so_y[m]);
+    } else {
+      const unsigned eo = on ? out_e : IE;
+      double* xo = a.xout[1 - cur];
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(xo + m * N + zo, nxy), eo, so_y[m]);
+    }
+  };
+
+  // ---- prologue: the first stage-input window, synchronously ---------------------------------
+  int hi = need_hi(pb0);
+  for (int pz = need_lo(pb0); pz <= hi; pz++) {
+    load_window(pz);
+    commit_window(pz);
+  }
+  __syncthreads();
+  // leave the same loads and (dropped) stores in flight, in the same order, as a plane step
+  load_b0(pb0);
+  load_window(hi + 1);
+  load_point(pb0 - 1);
+  store_plane(pb0 - 1, false);
+
+  // own-node values carried between plane steps: B at q - 1 and q; at q: F' z column,
+  // 1 / det F', det F
+  T Bqm[3] = {T(0), T(0), T(0)}, Bq[3] = {T(0), T(0), T(0)};
+  double Fzq[3] = {0.0, 0.0, 0.0};
+  double rDq = 0.0, Dq = 0.0;
+
+  for (int p = pb0; p <= z1; p++) {
     const int q = p - 1;
-    const bool out_here = (q >= z0 && q < z1 && tile_ok);
-    const long long out_zo = resolve(q, nz, bcz).i * nxy;     // uniform
-    unsigned out_o = out_here ? (unsigned)(gj_t * nx + gi_t) : 0u;
-    asm volatile("" : "+v"(out_o));
-
-    // 1. prefetch phase A of the next stage-input plane
-    const bool pre_plane = (p + 1 <= pb1) && (need_hi(p + 1) > need_hi(p));
-    const int pre_z = need_hi(p) + 1;
-    if (pre_plane) issue_a(pre_z);
-
-    // 2. F', det F' and B on the tile + 1-node halo of plane p
+    const bool qout = (q >= z0 && q < z1);
+    // 1. F', det F' and B on the tile + 1-node halo of plane p
+    T Bp[3] = {T(0), T(0), T(0)};
+    double Fzp[3] = {0.0, 0.0, 0.0};
+    double rDp = 0.0, Dp = 0.0;
     if (p <= pb1) {
-      const int sp = mod3(p);
-      const long long zo = resolve(p, nz, bcz).i * nxy;
+      const int sb = p & 1;
 #pragma unroll
       for (int r = 0; r < NP1; r++) {
         __builtin_amdgcn_sched_barrier(0);  // one field point at a time: bounds live temporaries
@@ -421,12 +465,12 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
           const int r1 = f1r[r], c1 = f1c[r];
           const int gi = i0 + c1 - 1, gj = j0 + r1 - 1;
           T B[3] = {T(0), T(0), T(0)};
-          if (f1xy[r] >= 0) {
+          if (f1e[r] != IE) {
             double F[3][3];
             jacobian(r1 + 1, c1 + 1, p, gi, gj, F);
             const double D = det3(F);
             const double rD = rcp_nr(D);
-            const T q0 = b0use[r][0], q1 = b0use[r][1], q2 = b0use[r][2];
+            const T q0 = b0r[r][0], q1 = b0r[r][1], q2 = b0r[r][2];
             if constexpr (MIXED) {
               const float fi = (float)rD;
 #pragma unroll
@@ -436,11 +480,14 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
               for (int m = 0; m < 3; m++) B[m] = (F[m][0] * q0 + F[m][1] * q1 + F[m][2] * q2) * rD;
             }
-            if (r == 0) {  // this thread's own tile point
+            if (r == 0) {  // this thread's own tile node
 #pragma unroll
-              for (int m = 0; m < 3; m++) Fzo[m] = F[m][2];
-              rDo = rD;
-              Do = D * inv8h3;
+              for (int m = 0; m < 3; m++) {
+                Fzp[m] = F[m][2];
+                Bp[m] = B[m];
+              }
+              rDp = rD;
+              Dp = D * inv8h3;
               if (STAGE1 && p >= z0 && p < z1 && gi < nx && gj < ny) {
                 // energy in FP64 from the FP64 Jacobian and B0'', weights zeta on line-tied faces
                 double zeta = 1.0;
@@ -451,75 +498,55 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int m = 0; m < 3; m++)
                   Bd[m] = (F[m][0] * (double)q0 + F[m][1] * (double)q1 + F[m][2] * (double)q2) * rD;
-                acc_E += zeta * (Bd[0] * Bd[0] + Bd[1] * Bd[1] + Bd[2] * Bd[2]) * Do;
-                acc_min = (Do < acc_min || Do != Do) ? Do : acc_min;
-                if (record_ck) {
-                  double* ck = a.ckpt + ck_slot * 3 * N;
-                  const unsigned o = (unsigned)f1xy[r];
-#pragma unroll
-                  for (int m = 0; m < 3; m++) (ck + zo + m * N)[o] = (xn + zo + m * N)[o];
-                }
+                acc_E += zeta * (Bd[0] * Bd[0] + Bd[1] * Bd[1] + Bd[2] * Bd[2]) * Dp;
+                acc_min = (Dp < acc_min || Dp != Dp) ? Dp : acc_min;
               }
             }
           }
 #pragma unroll
-          for (int m = 0; m < 3; m++) bs[sp][m][r1 * RX1 + c1] = B[m];
+          for (int m = 0; m < 3; m++) bs[sb][m][r1 * RX1 + c1] = B[m];
         }
       }
     }
-    // x and y columns of the tile point's Jacobian at plane q, read before the barrier: the
-    // commit at the end of this step reuses plane q's ring slot
-    double Fxy[3][3];
-    if (out_here) jac_xy(ty + 2, tx + 2, q, gi_t, gj_t, Fxy);
+    load_b0(p + 1 <= pb1 ? p + 1 : pb1);
+    // x and y columns of F' and the stage input at the tile node of plane q, read before
+    // the barrier: the commit below reuses plane q's ring slot
+    double Fxy[3][3], ycq[3];
+    if (qout) {
+      jac_xy(ty + 2, tx + 2, q, gi_t, gj_t, Fxy);
+      const int o = (ty + 2) * RX2 + tx + 2, sq = mod3(q);
+#pragma unroll
+      for (int m = 0; m < 3; m++) ycq[m] = ys[sq][m][o];
+    }
     __syncthreads();
 
+    // 2. commit the stage-input plane that field(p + 1) needs; issue the next one
+    if (p + 1 <= pb1 && need_hi(p + 1) > hi) {
+      hi++;
+      commit_window(hi);
+    }
+    load_window(hi + 1);
+
     // 3. current, force and velocity on the tile of plane q = p - 1
-    // (stage 6 first fetches the output node's x_n and k_j)
-    double sx[3] = {0, 0, 0};
-    T sk[4][3];
-    if constexpr (LAST) {
-      if (out_here && !diag_only) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-          const long long b = out_zo + m * N;
-          sx[m] = (xn + b)[out_o];
-          sk[0][m] = (static_cast<const T*>(a.k[0]) + b)[out_o];
-          sk[1][m] = (static_cast<const T*>(a.k[2]) + b)[out_o];
-          sk[2][m] = (static_cast<const T*>(a.k[3]) + b)[out_o];
-          sk[3][m] = (static_cast<const T*>(a.k[4]) + b)[out_o];
-        }
-      }
-    }
-    // fold phase A, issue phase B of the next plane and B0 of the next field plane (the
-    // previous B0 registers were consumed above)
-    if constexpr (NB > 0) {
-      if (pre_plane) {
-        fold_a();
-        issue_b(pre_z);
-      }
-    }
-    if (p + 1 <= pb1) issue_b0(p + 1, b0use);
-    if (out_here) {
+    if (qout) {
       const bool face = face_xy || (bcz == BC_LINE_TIED && (q == 0 || q == nz - 1));
       T u[3] = {T(0), T(0), T(0)};
       if (!face) {
         const int o = (ty + 1) * RX1 + (tx + 1);
-        const int sq = mod3(q), sm = mod3(q - 1), spl = mod3(q + 1);
+        const int sq = q & 1;
         T G[3][3];  // G'[a][m] = B_m(n + e_a) - B_m(n - e_a)
 #pragma unroll
         for (int m = 0; m < 3; m++) {
           G[0][m] = bs[sq][m][o + 1] - bs[sq][m][o - 1];
           G[1][m] = bs[sq][m][o + RX1] - bs[sq][m][o - RX1];
-          G[2][m] = bs[spl][m][o] - bs[sm][m][o];
+          G[2][m] = Bp[m] - Bqm[m];
         }
-        // the tile point's Jacobian at plane q: x and y columns recomputed from the stage
-        // input before the barrier, z column carried from the previous field step
         T Fq[3][3];
 #pragma unroll
         for (int m = 0; m < 3; m++) {
           Fq[m][0] = (T)Fxy[m][0];
           Fq[m][1] = (T)Fxy[m][1];
-          Fq[m][2] = (T)Fzi[m];
+          Fq[m][2] = (T)Fzq[m];
         }
         // c'_q = (F' e_b) . G'_a - (F' e_a) . G'_b, (a, b, q) = (y, z, x), (z, x, y), (x, y, z)
         T cq[3];
@@ -529,22 +556,21 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                 (Fq[0][2] * G[0][0] + Fq[1][2] * G[0][1] + Fq[2][2] * G[0][2]);
         cq[2] = Fq[0][1] * G[0][0] + Fq[1][1] * G[0][1] + Fq[2][1] * G[0][2] -
                 (Fq[0][0] * G[1][0] + Fq[1][0] * G[1][1] + Fq[2][0] * G[1][2]);
-        const T iD = (T)rDi;
+        const T iD = (T)rDq;
         T J[3];
 #pragma unroll
         for (int m = 0; m < 3; m++) J[m] = (Fq[m][0] * cq[0] + Fq[m][1] * cq[1] + Fq[m][2] * cq[2]) * iD;
-        const T Bq0 = bs[sq][0][o], Bq1 = bs[sq][1][o], Bq2 = bs[sq][2][o];
-        const T f0 = J[1] * Bq2 - J[2] * Bq1;
-        const T f1 = J[2] * Bq0 - J[0] * Bq2;
-        const T f2 = J[0] * Bq1 - J[1] * Bq0;
+        const T f0 = J[1] * Bq[2] - J[2] * Bq[1];
+        const T f1 = J[2] * Bq[0] - J[0] * Bq[2];
+        const T f2 = J[0] * Bq[1] - J[1] * Bq[0];
         const T gm = (T)gamma;
         u[0] = gm * f0;
         u[1] = gm * f1;
         u[2] = gm * f2;
-        if (STAGE1) {
+        if (STAGE1 && tile_ok) {
           const double F2 = (double)f0 * f0 + (double)f1 * f1 + (double)f2 * f2;
-          const double B2 = (double)Bq0 * Bq0 + (double)Bq1 * Bq1 + (double)Bq2 * Bq2;
-          acc_R2 += Di * F2;
+          const double B2 = (double)Bq[0] * Bq[0] + (double)Bq[1] * Bq[1] + (double)Bq[2] * Bq[2];
+          acc_R2 += Dq * F2;
           if (B2 > tau_B2) {
             const double ratio = sqrt(F2) / B2;
             acc_xi = (ratio > acc_xi || ratio != ratio) ? ratio : acc_xi;
@@ -553,60 +579,49 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
           }
         }
       }
-      if (diag_only) {
-        if (a.u_out) {
-          const double sc = (a.u_det_scale != 0.0) ? Di * a.u_det_scale : 1.0;
+      if constexpr (STAGE1) {
+        const double sc = (diag_only && a.u_det_scale != 0.0) ? Dq * a.u_det_scale : 1.0;
 #pragma unroll
-          for (int m = 0; m < 3; m++) (a.u_out + out_zo + m * N)[out_o] = (double)u[m] * sc;
+        for (int m = 0; m < 3; m++) {
+          so_k[m] = diag_only ? (T)((double)u[m] * sc) : u[m];
+          so_y[m] = ycq[m];
+        }
+      } else if constexpr (!LAST) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          double y = ycq[m];
+#pragma unroll
+          for (int j = 0; j < NPK; j++) y = fma(cy[j], (double)pk[j][m], y);
+          so_y[m] = fma(cys, (double)u[m], y);
+          so_k[m] = u[m];
         }
       } else {
-        if constexpr (!LAST) {
-          T* __restrict__ ks = static_cast<T*>(a.k[S - 1]);
+        // x_{n+1} = x_n + dt sum b5_s k_s;  err = dt sum (b5_s - b4_s) k_s
 #pragma unroll
-          for (int m = 0; m < 3; m++) (ks + out_zo + m * N)[out_o] = u[m];
-        } else {
-          // x_{n+1} = x_n + dt sum b5_s k_s;  err = dt sum (b5_s - b4_s) k_s
-          double* __restrict__ xo = a.xout[1 - cur];
-#pragma unroll
-          for (int m = 0; m < 3; m++) {
-            const double v1 = sk[0][m], v3 = sk[1][m], v4 = sk[2][m], v5 = sk[3][m], v6 = (double)u[m];
-            const double s5 = CK::b5[0] * v1 + CK::b5[2] * v3 + CK::b5[3] * v4 + CK::b5[5] * v6;
-            const double se = (CK::b5[0] - CK::b4[0]) * v1 + (CK::b5[2] - CK::b4[2]) * v3 +
-                              (CK::b5[3] - CK::b4[3]) * v4 + (CK::b5[4] - CK::b4[4]) * v5 +
-                              (CK::b5[5] - CK::b4[5]) * v6;
-            (xo + out_zo + m * N)[out_o] = sx[m] + dt * s5;
-            const double err = fabs(dt * se);
-            acc_lam = (err > acc_lam || err != err) ? err : acc_lam;
-          }
+        for (int m = 0; m < 3; m++) {
+          const double v1 = pk[0][m], v3 = pk[1][m], v4 = pk[2][m], v5 = pk[3][m], v6 = (double)u[m];
+          const double s5 = CK::b5[0] * v1 + CK::b5[2] * v3 + CK::b5[3] * v4 + CK::b5[5] * v6;
+          const double se = (CK::b5[0] - CK::b4[0]) * v1 + (CK::b5[2] - CK::b4[2]) * v3 +
+                            (CK::b5[3] - CK::b4[3]) * v4 + (CK::b5[4] - CK::b4[4]) * v5 +
+                            (CK::b5[5] - CK::b4[5]) * v6;
+          so_y[m] = px[m] + dt * s5;
+          const double err = tile_ok ? fabs(dt * se) : 0.0;
+          acc_lam = (err > acc_lam || err != err) ? err : acc_lam;
         }
       }
     }
-
-    // 4. commit the prefetched plane (its ring slot held the plane B(p) no longer needs)
-    if (pre_plane) commit_plane(pre_z);
+    load_point(p);  // output node of the next plane step
+    store_plane(q, qout);
     __syncthreads();
-  };
 
-  // prologue: the first window, synchronously; B0 of the first plane
-  for (int pz = need_lo(pb0); pz <= need_hi(pb0); pz++) {
-    issue_a(pz);
-    if constexpr (NB > 0) {
-      fold_a();
-      issue_b(pz);
-    }
-    commit_plane(pz);
-  }
-  double Fzprev[3] = {0, 0, 0}, Fzcur[3] = {0, 0, 0};
-  double rDprev = 0.0, rDcur = 0.0, Dprev = 0.0, Dcur = 0.0;
-  T b0reg[NP1][3];
-  issue_b0(pb0, b0reg);
-  __syncthreads();
-  for (int p = pb0; p <= pb1 + 1; p++) {
-    plane(p, Fzprev, rDprev, Dprev, Fzcur, rDcur, Dcur, b0reg);
 #pragma unroll
-    for (int m = 0; m < 3; m++) Fzprev[m] = Fzcur[m];
-    rDprev = rDcur;
-    Dprev = Dcur;
+    for (int m = 0; m < 3; m++) {
+      Bqm[m] = Bq[m];
+      Bq[m] = Bp[m];
+      Fzq[m] = Fzp[m];
+    }
+    rDq = rDp;
+    Dq = Dp;
   }
 
   // ---- workgroup reductions -> partial records -----------------------------------------

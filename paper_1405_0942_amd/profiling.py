@@ -1,0 +1,165 @@
+"""Summaries of rocprofv3 output for the stage sweeps: HBM bytes per launch from the
+FETCH_SIZE / WRITE_SIZE counters, calibrated on a device copy of known size.
+
+The two counters come from two separate `rocprofv3 --pmc` runs of the same program (one
+counter each).  Each run also holds the 1 GiB device-to-device copy that bench.py makes
+to measure copy bandwidth; its reading against the 1 GiB it moves gives the scale of each
+counter on this device.
+
+    python -m paper_1405_0942_amd.profiling traffic --fetch DIR --write DIR \\
+        --workload abc_256 --precision fp64 --command "..." > profiles/<name>.txt
+
+`read_traffic` parses such a summary; `kernel_source_hash` identifies the kernel source
+the counters were taken on (a summary of other source is stale).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/stage.hip", "csrc/relax_device.h")
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _counter_csv(run_dir: str) -> str:
+    hits = sorted(glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *counter_collection.csv under {run_dir}")
+    return hits[0]
+
+
+def read_counter(run_dir: str, counter: str):
+    """[(dispatch_id, kernel_name, value in counter units)] of one --pmc run, dispatch order."""
+    rows = []
+    with open(_counter_csv(run_dir), newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def _stage_of(name: str):
+    m = re.search(r"stage_kernel<(\d), (false|true), (false|true)>", name)
+    if not m:
+        return None
+    return int(m.group(1)), m.group(2) == "true"
+
+
+def traffic(fetch_dir: str, write_dir: str, mixed: bool):
+    """Per-stage mean HBM bytes per launch, and the two calibration factors."""
+    fetch = read_counter(fetch_dir, "FETCH_SIZE")
+    write = read_counter(write_dir, "WRITE_SIZE")
+    if [d for d, _, _ in fetch] != [d for d, _, _ in write]:
+        raise ValueError("the two runs dispatched different kernels")
+    kib = COPY_BYTES / 1024.0
+    cal = [(f, w) for (_, n, f), (_, _, w) in zip(fetch, write)
+           if "copyBuffer" in n and abs(w - kib) < 0.01 * kib]
+    if not cal:
+        raise ValueError("no 1 GiB device copy among the dispatches")
+    f_scale = kib / (sum(f for f, _ in cal) / len(cal))
+    w_scale = kib / (sum(w for _, w in cal) / len(cal))
+    per = collections.defaultdict(list)
+    for (_, n, f), (_, _, w) in zip(fetch, write):
+        st = _stage_of(n)
+        if st is None or st[1] != mixed:
+            continue
+        per[st[0]].append((f, w))
+    out = {}
+    for s, v in sorted(per.items()):
+        fb = sum(f for f, _ in v) / len(v) * f_scale * 1024.0
+        wb = sum(w for _, w in v) / len(v) * w_scale * 1024.0
+        out[s] = {"launches": len(v), "fetch_bytes": fb, "write_bytes": wb, "bytes": fb + wb}
+    return out, f_scale, w_scale
+
+
+def read_traffic(path: str):
+    """key: value lines of a traffic summary, or None if there is no such file."""
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^([A-Za-z0-9_]+):\s*(.*?)\s*$", line)
+            if m:
+                rec[m.group(1)] = m.group(2)
+    return rec
+
+
+def kernel_stats(run_dir: str):
+    """Rows of a `rocprofv3 --kernel-trace --stats` run: (name, calls, average ns, min, max)."""
+    hits = sorted(glob.glob(os.path.join(run_dir, "**", "*kernel_stats.csv"), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *kernel_stats.csv under {run_dir}")
+    rows = []
+    with open(hits[0], newline="") as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"]),
+                         float(r["Percentage"])))
+    return rows
+
+
+def _short(name: str) -> str:
+    name = name.replace("relax::(anonymous namespace)::", "").replace("(relax::SweepArgs)", "")
+    name = re.sub(r"^void ", "", name)
+    return re.sub(r"\(.*\)$", "", name) if "stage_kernel" not in name else name
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("kernel-stats")
+    k.add_argument("--trace", required=True, help="rocprofv3 output directory of a --kernel-trace --stats run")
+    k.add_argument("--title", required=True)
+    k.add_argument("--command", required=True, help="the profiled command, recorded in the summary")
+    k.add_argument("--top", type=int, default=12)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True, help="rocprofv3 output directory of the FETCH_SIZE run")
+    t.add_argument("--write", required=True, help="rocprofv3 output directory of the WRITE_SIZE run")
+    t.add_argument("--workload", required=True)
+    t.add_argument("--precision", choices=["fp64", "fp32-mixed"], default="fp64")
+    t.add_argument("--nodes", type=int, required=True, help="grid nodes (for bytes per node)")
+    t.add_argument("--command", required=True, help="the profiled command, recorded in the summary")
+    args = ap.parse_args(argv)
+    w = sys.stdout.write
+    if args.cmd == "kernel-stats":
+        w(f"# {args.title}\n\n")
+        w("Command (from the repository root):\n\n")
+        w(f"    {args.command}\n\n")
+        w("| kernel | calls | avg ms | min ms | max ms | % of GPU time |\n|---|---:|---:|---:|---:|---:|\n")
+        for name, calls, avg, mn, mx, pct in kernel_stats(args.trace)[: args.top]:
+            w(f"| `{_short(name)}` | {calls} | {avg / 1e6:.4f} | {mn / 1e6:.4f} | {mx / 1e6:.4f} | {pct:.2f} |\n")
+        return
+    per, fs, ws = traffic(args.fetch, args.write, args.precision == "fp32-mixed")
+    w(f"# HBM traffic per launch of the stage sweeps, {args.workload}, {args.precision}\n")
+    w("# rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE, one run each:\n")
+    w(f"#   {args.command}\n")
+    w("# counters scaled by their reading on the 1 GiB device copy of the same runs\n")
+    w(f"source_sha256: {kernel_source_hash()}\n")
+    w(f"fetch_scale: {fs:.4f}\n")
+    w(f"write_scale: {ws:.4f}\n")
+    for s, v in per.items():
+        w(f"stage{s}_launches: {v['launches']}\n")
+        w(f"stage{s}_fetch_bytes_per_launch: {v['fetch_bytes']:.0f}\n")
+        w(f"stage{s}_write_bytes_per_launch: {v['write_bytes']:.0f}\n")
+        w(f"stage{s}_bytes_per_launch: {v['bytes']:.0f}\n")
+        w(f"stage{s}_bytes_per_node: {v['bytes'] / args.nodes:.1f}\n")
+
+
+if __name__ == "__main__":
+    main()
