@@ -136,6 +136,33 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2 * n * 8 / sec / 1e9
 
 
+def adjoint_cost(R, torch, W, steps=200, every=20):
+    """Reverse-mode cost on the braid gradient workload (64x64x192, twist amplitudes
+    U(0.5, 1.5) with seed 4): K adaptive FP64 steps recording dt and checkpoints every
+    `every` steps, then relax_backward of E_M(x_K) (which recomputes each segment)."""
+    w = W.braid(64, 192, seed=4)
+    cfg = R.make_config(w.grid, precision=R.RELAX_FP64, dt0=w.dt0, tol=w.tol, adaptive=True, record=True,
+                        checkpoint_every=every)
+    x0 = torch.from_numpy(w.x0).cuda()
+    B0 = torch.from_numpy(w.B0).cuda()
+    with R.Relaxation(cfg, x0, B0, K_record=steps) as r:  # first use: code objects loaded
+        r.step(every, diag=False)
+        r.backward(1.0, 0.0)
+    with R.Relaxation(cfg, x0, B0, K_record=steps) as r:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r.step(steps, diag=False)
+        torch.cuda.synchronize()
+        tf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r.backward(1.0, 0.0)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+    return {"workload": f"{w.name}, twist amplitudes U(0.5,1.5) seed 4", "steps": steps,
+            "checkpoint_every": every, "forward_ms_per_step": tf * 1e3 / steps,
+            "backward_ms_per_step": tb * 1e3 / steps, "backward_over_forward": tb / tf}
+
+
 def cpu_baseline(w, steps, dt):
     import oracle
     log(f"cpu baseline: oracle, {steps} fixed-dt steps on the full grid, {oracle.threads()} threads")
@@ -158,6 +185,7 @@ def main():
     ap.add_argument("--dt0", type=float, default=1e-3)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost figure")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -214,6 +242,9 @@ def main():
                               "rejects_in_timed_steps": mm["rejects"], "roofline": mm["roofline"],
                               "step_hbm_GBs_algorithmic": mm["step_GBs"], "kernels": mm["kernels"],
                               "E_last_rel_diff_vs_fp64": abs(mm["E_last"] - m["E_last"]) / abs(m["E_last"])}
+    if not args.no_adjoint:
+        log("adjoint cost: braid 64x64x192, 200 steps, checkpoints every 20")
+        line["adjoint"] = adjoint_cost(R, torch, W)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, dt=args.dt0)
     print(json.dumps(line), flush=True)

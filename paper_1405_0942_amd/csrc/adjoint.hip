@@ -13,14 +13,29 @@
 //   pull-back: Fbar' += (rD Bbar) B0''^T,  B0bar'' += F'^T Bbar rD,  rDbar += Bbar . F'B0'',
 //   Dbar' = -rD^2 rDbar,  Fbar' += Dbar' cof(F'),
 //   ybar = D^T Fbar'                                           (transpose of the differences).
-// Note Gbar'(n) needs only F', rD, B and ubar at n, so Bbar(m) needs the stage input on a
-// 2-node halo of m, the same footprint as the forward sweep.  adj_field_kernel forms Fbar'
-// (9 values per node) and accumulates B0bar''; adj_gather_kernel applies D^T.
+// Gbar'(n) needs only F', rD, B and ubar at n, so Bbar(m) needs the stage input on a 2-node
+// halo of m, the same footprint as the forward sweep.  adj_field_kernel forms Fbar' (9 values
+// per node) and accumulates B0bar''; adj_gather_kernel applies D^T and, pointwise, assembles
+// the cotangent of the previous stage's k (the Runge-Kutta transpose, see below).
 //
-// Seeds (seed_kernel mode of adj_field_kernel): E_M = 1/2 sum zeta |B|^2 det F dV adds
-// kappa D' B to Bbar and 1/2 kappa |B|^2 to Dbar' (kappa = zeta dV / (8 hx hy hz));
-// R2 = 1/2 sum_interior det F |f|^2 dV enters through ubar = det F dV f / gamma (read from a
-// buffer) plus 1/2 |f|^2 dV / (8 hx hy hz) on Dbar'.
+// Runge-Kutta transpose of one step x_{n+1} = x_n + dt sum_s b5_s k_s, k_s = u(y_s),
+// y_s = x_n + dt sum_{j<s} a_sj k_j:
+//   kbar_s = dt (b5_s xbar_{n+1} + sum_{t>s} a_ts ybar_t),  ybar_s = (du/dy)(y_s)^T kbar_s,
+//   xbar_n = xbar_{n+1} + sum_s ybar_s.
+// The stage-6 field sweep scales xbar_{n+1} itself; the gather of stage t writes ybar_t and
+// kbar_{t-1}, which the field sweep of stage t - 1 reads.
+//
+// Seeds (seed mode of adj_field_kernel): E_M = 1/2 sum zeta |B|^2 det F dV adds kappa D' B to
+// Bbar and 1/2 kappa |B|^2 to Dbar' (kappa = zeta dV / (8 hx hy hz)); R2 = 1/2 sum_interior
+// det F |f|^2 dV enters through ubar = det F dV f / gamma (read from a buffer) plus
+// 1/2 |f|^2 dV / (8 hx hy hz) on Dbar'.
+//
+// The field sweep is laid out like the forward stage sweep: a 64 x 4 tile marching up a
+// z-chunk, the stage input in an LDS ring of three planes (stages 3..6 stencil the stored
+// y_s of the step), B in a ring of two planes, Gbar'_x and Gbar'_y in one plane that is
+// transposed in-plane as soon as it is formed; buffer loads with masked-off lanes (offsets
+// past the record count) issued one plane step ahead, so no divergent branch surrounds a
+// memory instruction and the waits are exact.
 #include "relax_device.h"
 
 namespace relax {
@@ -48,6 +63,21 @@ __device__ __forceinline__ AxisIdx resolve(int v, int n, int bc) {
   return r;
 }
 
+// element index of a masked-off lane (scaled by 8 it lies past every plane's record count)
+constexpr unsigned IE = 1u << 28;
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer resource, gfx9 encoding
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base, unsigned nxy) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)(nxy * 8u), RSRC_WORD3);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned e) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned e, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, 0);
+}
+
 __device__ __forceinline__ int logical_block(int bid, int nb) {
   const int q = nb >> 3, r = nb & 7;
   const int xcd = bid & 7, j = bid >> 3;
@@ -59,6 +89,14 @@ __device__ __forceinline__ double det3(const double F[3][3]) {
          F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
 }
 
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ void cross(const double a[3], const double b[3], double o[3]) {
   o[0] = a[1] * b[2] - a[2] * b[1];
   o[1] = a[2] * b[0] - a[0] * b[2];
@@ -66,29 +104,28 @@ __device__ __forceinline__ void cross(const double a[3], const double b[3], doub
 }
 
 template <int S, bool XYP, bool SEED>
-__global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
-  constexpr int NK = (S > 1) ? S - 1 : 1;
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) void adj_field_kernel(AdjArgs a) {
+  constexpr bool WK = (!SEED && S == 2);  // the window carries k_1 too
   constexpr int NP2 = (RY2 * RX2 + NTHREADS - 1) / NTHREADS;
   constexpr int NP1 = (RY1 * RX1 + NTHREADS - 1) / NTHREADS;
 
   const Geometry& g = a.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const long long N = g.N;
-  const long long nxy = (long long)nx * ny;
+  const unsigned nxy = (unsigned)nx * (unsigned)ny;
   const int bcx = XYP ? BC_PERIODIC : g.bc[0];
   const int bcy = XYP ? BC_PERIODIC : g.bc[1];
   const int bcz = g.bc[2];
   const double gamma = a.gamma;
 
-  // stage input y_S = x + dt sum_{j<S} a_Sj k_j; cotangent ubar = dt (b5_S xbar' + sum_{t>S} a_tS ybar_t)
   const double dt = SEED ? 0.0 : *a.dt;
-  double cka[NK];
-#pragma unroll
-  for (int j = 0; j < NK; j++) cka[j] = (S > 1) ? dt * CK::a[S - 1][j] : 0.0;
-  double cub[7];
-#pragma unroll
-  for (int t = 0; t < 7; t++) cub[t] = (t > S && t <= 6) ? dt * CK::a[t > 0 ? t - 1 : 0][S < 6 ? S - 1 : 0] : 0.0;
-  const double cux = dt * CK::b5[S - 1];
+  const double c21 = dt * CK::a[1][0];
+  // the cotangent of u: seed buffer, dt b5_6 xbar_{n+1} (stage 6), or the gathered kbar_s
+  const bool v_on = !SEED || a.useed != nullptr;
+  const double* __restrict__ vsrc = SEED ? (a.useed ? a.useed : a.B0) : (S == 6 ? a.xbar : a.ubar);
+  const double cv = (!SEED && S == 6) ? dt * CK::b5[5] : 1.0;
+  const double* __restrict__ wsrc = (SEED || S <= 2) ? a.x : a.y[S > 2 ? S - 3 : 0];
+  const double* __restrict__ k1p = a.k[0];
 
   const int lb = logical_block(blockIdx.x, g.nblocks);
   const int tile_x = lb % g.tiles[0];
@@ -100,21 +137,28 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
 
-  __shared__ double ys[3][3][RY2 * RX2];
-  __shared__ double bs[3][3][RY1 * RX1];
-  __shared__ double gxy[2][6][RY1 * RX1];  // Gbar'_x (0..2) and Gbar'_y (3..5), planes q and p
+  __shared__ double ys[3][3][RY2 * RX2];  // stage input, ring of 3 planes
+  __shared__ double bs[2][3][RY1 * RX1];  // B, ring of 2 planes
+  __shared__ double gxy[6][RY1 * RX1];    // Gbar'_x (0..2) and Gbar'_y (3..5) of the newest plane
+
+  auto zload = [&](int pz) {
+    if (bcz == BC_PERIODIC) return resolve(pz, nz, bcz).i;
+    return min(max(pz, 0), nz - 1);
+  };
 
   // index tables (as in the forward sweep)
-  int w2xy[NP2], w2w[NP2];
+  unsigned w2e[NP2];
+  int w2w[NP2];
 #pragma unroll
   for (int r = 0; r < NP2; r++) {
     const int e = tid + r * NTHREADS;
     const int row = e / RX2, col = e - row * RX2;
     const AxisIdx rx = resolve(i0 + col - 2, nx, bcx), ry = resolve(j0 + row - 2, ny, bcy);
-    w2xy[r] = (e < RY2 * RX2 && rx.ok && ry.ok) ? ry.i * nx + rx.i : -1;
+    w2e[r] = (e < RY2 * RX2 && rx.ok && ry.ok) ? (unsigned)(ry.i * nx + rx.i) : IE;
     w2w[r] = (ry.w << 16) + (rx.w & 0xffff);
   }
-  int f1xy[NP1], f1r[NP1], f1c[NP1];
+  unsigned f1e[NP1];
+  int f1r[NP1], f1c[NP1];
 #pragma unroll
   for (int r = 0; r < NP1; r++) {
     const int e = tid + r * NTHREADS;
@@ -137,42 +181,99 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
       }
     }
     const AxisIdx rx = resolve(i0 + c1 - 1, nx, bcx), ry = resolve(j0 + r1 - 1, ny, bcy);
-    f1xy[r] = (e < RY1 * RX1 && rx.ok && ry.ok) ? ry.i * nx + rx.i : -1;
+    f1e[r] = (e < RY1 * RX1 && rx.ok && ry.ok) ? (unsigned)(ry.i * nx + rx.i) : IE;
     f1r[r] = (e < RY1 * RX1) ? r1 : -1;
     f1c[r] = c1;
   }
+  const int gi_t = i0 + tx, gj_t = j0 + ty;
+  const bool tile_ok = (gi_t < nx) && (gj_t < ny);
+  const unsigned out_e = tile_ok ? (unsigned)(gj_t * nx + gi_t) : IE;
 
-  auto load_plane = [&](int pz) {
-    const AxisIdx rz = resolve(pz, nz, bcz);
-    const long long zo = rz.i * nxy;
-    const int slot = mod3(pz);
+  auto face_at = [&](int gi, int gj, int p) {
+    return (bcx == BC_LINE_TIED && (gi == 0 || gi == nx - 1)) || (bcy == BC_LINE_TIED && (gj == 0 || gj == ny - 1)) ||
+           (bcz == BC_LINE_TIED && (p == 0 || p == nz - 1));
+  };
+
+  // ---- loads, issued one plane step ahead of their use ---------------------------------------
+  double wx[NP2][3];
+  double wk[WK ? NP2 : 1][3];
+  double b0r[NP1][3], vr[NP1][3];
+  double bbr[3];  // B0bar'' at the output node
+  auto load_window = [&](int pz) {
+    const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
-    for (int r = 0; r < NP2; r++) {
-      const int e = tid + r * NTHREADS;
-      if (e < RY2 * RX2) {
-        double v[3] = {0.0, 0.0, 0.0};
-        if (w2xy[r] >= 0) {
-          const long long idx = zo + w2xy[r];
+    for (int m = 0; m < 3; m++) {
+      const auto rs = plane_rsrc(wsrc + m * N + zo, nxy);
 #pragma unroll
-          for (int m = 0; m < 3; m++) {
-            double y = a.x[idx + m * N];
-            if constexpr (S > 1) {
+      for (int r = 0; r < NP2; r++) wx[r][m] = bload(rs, w2e[r]);
+    }
+    if constexpr (WK) {
 #pragma unroll
-              for (int j = 0; j < S - 1; j++) y = fma(cka[j], a.k[j][idx + m * N], y);
-            }
-            v[m] = y;
-          }
-          v[0] += (double)(short)(w2w[r] & 0xffff) * g.period[0];
-          v[1] += (double)(w2w[r] >> 16) * g.period[1];
-          v[2] += rz.w * g.period[2];
-        }
+      for (int m = 0; m < 3; m++) {
+        const auto rs = plane_rsrc(k1p + m * N + zo, nxy);
 #pragma unroll
-        for (int m = 0; m < 3; m++) ys[slot][m][e] = v[m];
+        for (int r = 0; r < NP2; r++) wk[r][m] = bload(rs, w2e[r]);
       }
     }
   };
+  auto commit_window = [&](int pz) {
+    const AxisIdx rz = resolve(pz, nz, bcz);
+    const int slot = mod3(pz);
+    const double shz = rz.w * g.period[2];
+#pragma unroll
+    for (int r = 0; r < NP2; r++) {
+      const int e = tid + r * NTHREADS;
+      const bool ok = (w2e[r] != IE);
+      double v[3];
+#pragma unroll
+      for (int m = 0; m < 3; m++) {
+        double y = wx[r][m];
+        if constexpr (WK) y = fma(c21, wk[r][m], y);
+        v[m] = y;
+      }
+      v[0] += (double)(short)(w2w[r] & 0xffff) * g.period[0];
+      v[1] += (double)(w2w[r] >> 16) * g.period[1];
+      v[2] += shz;
+      if (e < RY2 * RX2) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) ys[slot][m][e] = ok ? v[m] : 0.0;
+      }
+    }
+  };
+  auto load_field = [&](int pz) {
+    const long long zo = (long long)zload(pz) * nxy;
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+      const auto rb = plane_rsrc(a.B0 + m * N + zo, nxy);
+      const auto rv = plane_rsrc(vsrc + m * N + zo, nxy);
+#pragma unroll
+      for (int r = 0; r < NP1; r++) {
+        b0r[r][m] = bload(rb, f1e[r]);
+        vr[r][m] = bload(rv, v_on ? f1e[r] : IE);
+      }
+    }
+  };
+  auto load_point = [&](int pz) {
+    const bool on = (pz >= z0 && pz < z1);
+    const long long zo = (long long)zload(pz) * nxy;
+#pragma unroll
+    for (int m = 0; m < 3; m++) bbr[m] = bload(plane_rsrc(a.B0bar + m * N + zo, nxy), on ? out_e : IE);
+  };
+  double so_F[9], so_B[3];
+#pragma unroll
+  for (int i = 0; i < 9; i++) so_F[i] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; m++) so_B[m] = 0.0;
+  auto store_point = [&](int qz, bool on) {
+    const long long zo = (long long)zload(qz) * nxy;
+    const unsigned eo = on ? out_e : IE;
+#pragma unroll
+    for (int i = 0; i < 9; i++) bstore(plane_rsrc(a.Fbar + i * N + zo, nxy), eo, so_F[i]);
+#pragma unroll
+    for (int m = 0; m < 3; m++) bstore(plane_rsrc(a.B0bar + m * N + zo, nxy), eo, so_B[m]);
+  };
 
-  auto jacobian = [&](int r, int c, int p, int gi, int gj, double F[3][3]) {
+  auto jac_xy = [&](int r, int c, int p, int gi, int gj, double F[3][3]) {
     const int o = r * RX2 + c;
     const int sp = mod3(p);
 #pragma unroll
@@ -191,6 +292,10 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
       else
         F[m][1] = 3.0 * yc[o] - 4.0 * yc[o - RX2] + yc[o - 2 * RX2];
     }
+  };
+  auto jacobian = [&](int r, int c, int p, int gi, int gj, double F[3][3]) {
+    jac_xy(r, c, p, gi, gj, F);
+    const int o = r * RX2 + c;
     if (bcz == BC_PERIODIC || (p > 0 && p < nz - 1)) {
       const int sa = mod3(p + 1), sb = mod3(p - 1);
 #pragma unroll
@@ -205,68 +310,58 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
     }
   };
 
-  // cotangent ubar at node index idx (zero on line-tied faces)
-  auto ubar_at = [&](long long idx, double ub[3]) {
-#pragma unroll
-    for (int m = 0; m < 3; m++) {
-      double v;
-      if constexpr (SEED) {
-        v = a.useed ? a.useed[idx + m * N] : 0.0;
-      } else {
-        v = cux * a.xbar[idx + m * N];
-#pragma unroll
-        for (int t = S + 1; t <= 6; t++) v = fma(cub[t], a.ybar[t][idx + m * N], v);
-      }
-      ub[m] = v;
-    }
-  };
-
   const bool perz = (bcz == BC_PERIODIC);
   const int pb0 = perz ? z0 - 1 : max(z0 - 1, 0);
   const int pb1 = perz ? z1 : min(z1, nz - 1);
   auto need_hi = [&](int p) { return perz ? p + 1 : (p == 0 ? 2 : (p == nz - 1 ? p : p + 1)); };
   auto need_lo = [&](int p) { return perz ? p - 1 : (p == 0 ? 0 : (p == nz - 1 ? p - 2 : p - 1)); };
-  auto face_at = [&](int gi, int gj, int p) {
-    return (bcx == BC_LINE_TIED && (gi == 0 || gi == nx - 1)) || (bcy == BC_LINE_TIED && (gj == 0 || gj == ny - 1)) ||
-           (bcz == BC_LINE_TIED && (p == 0 || p == nz - 1));
-  };
 
-  const int gi_t = i0 + tx, gj_t = j0 + ty;
-  const bool tile_ok = (gi_t < nx) && (gj_t < ny);
+  // prologue: the first stage-input window, then the loads and (dropped) stores a plane step
+  // leaves in flight, in the same order
+  int hi = need_hi(pb0);
+  for (int pz = need_lo(pb0); pz <= hi; pz++) {
+    load_window(pz);
+    commit_window(pz);
+  }
+  __syncthreads();
+  load_field(pb0);
+  load_window(hi + 1);
+  load_point(pb0 - 1);
+  store_point(pb0 - 1, false);
 
-  double Fprev[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Fcur[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double rDprev = 0.0, rDcur = 0.0;
-  double ubprev[3] = {0, 0, 0}, ubcur[3] = {0, 0, 0};
-  double gzm[3] = {0, 0, 0}, gzq[3] = {0, 0, 0}, gzp[3] = {0, 0, 0};  // Gbar'_z at the tile point, planes q-1, q, q+1
+  // own-node values carried between plane steps (q = p - 1 is the output plane)
+  double Fzq[3] = {0, 0, 0};  // z column of F' at q (the x and y columns are re-read from the ring)
+  double rDq = 0.0;
+  double ubq[3] = {0, 0, 0}, Bq[3] = {0, 0, 0}, Bqm[3] = {0, 0, 0}, b0q[3] = {0, 0, 0};
+  double gzqm[3] = {0, 0, 0}, gzq[3] = {0, 0, 0};  // Gbar'_z at q - 1 and q
+  double Bbxyq[3] = {0, 0, 0};                     // in-plane transpose of Gbar' at q
+  const int ot = (ty + 1) * RX1 + (tx + 1);
 
-  int loaded_hi = need_lo(pb0) - 1;
-  for (int p = pb0; p <= pb1 + 1; p++) {
+  for (int p = pb0; p <= z1; p++) {
+    const int q = p - 1;
+    const bool qout = (q >= z0 && q < z1);
+    // 1. B, Gbar'_x, Gbar'_y on the tile + 1-node halo of plane p; own-node values
+    double Fzp[3] = {0, 0, 0};
+    double rDp = 0.0, ubp[3] = {0, 0, 0}, Bp[3] = {0, 0, 0}, b0p[3] = {0, 0, 0}, gzp[3] = {0, 0, 0};
     if (p <= pb1) {
-      if (loaded_hi < need_lo(p) - 1) loaded_hi = need_lo(p) - 1;
-      while (loaded_hi < need_hi(p)) load_plane(++loaded_hi);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 3; m++) gzp[m] = 0.0;
-    if (p <= pb1) {
-      const int sp = mod3(p), gb = p & 1;
-      const long long zo = resolve(p, nz, bcz).i * nxy;
+      const int sb = p & 1;
 #pragma unroll
       for (int r = 0; r < NP1; r++) {
+        __builtin_amdgcn_sched_barrier(0);
         if (f1r[r] >= 0) {
           const int r1 = f1r[r], c1 = f1c[r];
           const int gi = i0 + c1 - 1, gj = j0 + r1 - 1;
           double B[3] = {0, 0, 0}, Gx[3] = {0, 0, 0}, Gy[3] = {0, 0, 0}, Gz[3] = {0, 0, 0}, ub[3] = {0, 0, 0};
-          if (f1xy[r] >= 0) {
-            const long long idx = zo + f1xy[r];
+          if (f1e[r] != IE) {
             double F[3][3];
             jacobian(r1 + 1, c1 + 1, p, gi, gj, F);
-            const double rD = 1.0 / det3(F);
-            const double q0 = a.B0[idx], q1 = a.B0[idx + N], q2 = a.B0[idx + 2 * N];
+            const double rD = rcp_nr(det3(F));
+            const double q0 = b0r[r][0], q1 = b0r[r][1], q2 = b0r[r][2];
 #pragma unroll
             for (int m = 0; m < 3; m++) B[m] = (F[m][0] * q0 + F[m][1] * q1 + F[m][2] * q2) * rD;
             if (!face_at(gi, gj, p)) {
-              ubar_at(idx, ub);
+#pragma unroll
+              for (int m = 0; m < 3; m++) ub[m] = cv * vr[r][m];
               const double fb[3] = {gamma * ub[0], gamma * ub[1], gamma * ub[2]};
               double Jb[3];
               cross(B, fb, Jb);
@@ -283,47 +378,64 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
             if (r == 0) {
 #pragma unroll
               for (int m = 0; m < 3; m++) {
-#pragma unroll
-                for (int n2 = 0; n2 < 3; n2++) Fcur[m][n2] = F[m][n2];
-                ubcur[m] = ub[m];
+                Fzp[m] = F[m][2];
+                ubp[m] = ub[m];
+                Bp[m] = B[m];
+                b0p[m] = b0r[r][m];
                 gzp[m] = Gz[m];
               }
-              rDcur = rD;
+              rDp = rD;
             }
           }
           const int o = r1 * RX1 + c1;
 #pragma unroll
           for (int m = 0; m < 3; m++) {
-            bs[sp][m][o] = B[m];
-            gxy[gb][m][o] = Gx[m];
-            gxy[gb][3 + m][o] = Gy[m];
+            bs[sb][m][o] = B[m];
+            gxy[m][o] = Gx[m];
+            gxy[3 + m][o] = Gy[m];
           }
         }
       }
     }
+    load_field(p + 1 <= pb1 ? p + 1 : pb1);
+    // x and y columns of F' at the own node of plane q, read before the barrier: the commit
+    // below reuses plane q's ring slot
+    double F[3][3];
+    if (qout) {
+      jac_xy(ty + 2, tx + 2, q, gi_t, gj_t, F);
+#pragma unroll
+      for (int m = 0; m < 3; m++) F[m][2] = Fzq[m];
+    }
     __syncthreads();
 
-    const int q = p - 1;
-    if (q >= z0 && q < z1 && tile_ok) {
-      const AxisIdx rzq = resolve(q, nz, bcz);
-      const long long idx = rzq.i * nxy + (long long)gj_t * nx + gi_t;
-      const int o = (ty + 1) * RX1 + (tx + 1);
-      const int sq = mod3(q), gb = q & 1;
+    // 2. commit the stage-input plane field(p + 1) needs; issue the next one
+    if (p + 1 <= pb1 && need_hi(p + 1) > hi) {
+      hi++;
+      commit_window(hi);
+    }
+    load_window(hi + 1);
+
+    // 3. in-plane transpose of Gbar' at the own node of plane p (used by the next step)
+    double Bbxyp[3];
+#pragma unroll
+    for (int m = 0; m < 3; m++)
+      Bbxyp[m] = (gxy[m][ot - 1] - gxy[m][ot + 1]) + (gxy[3 + m][ot - RX1] - gxy[3 + m][ot + RX1]);
+
+    // 4. the transpose at the own node of plane q
+    if (qout) {
       const bool interior = !face_at(gi_t, gj_t, q);
-      const double Bm[3] = {bs[sq][0][o], bs[sq][1][o], bs[sq][2][o]};
       double Bb[3] = {0, 0, 0};
       double Fb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
       double rDb = 0.0, Db_direct = 0.0;
       if (interior) {
-        const int sm = mod3(q - 1), spl = mod3(q + 1);
+        const int sq = q & 1;
         double G[3][3];  // G[a][m]
 #pragma unroll
         for (int m = 0; m < 3; m++) {
-          G[0][m] = bs[sq][m][o + 1] - bs[sq][m][o - 1];
-          G[1][m] = bs[sq][m][o + RX1] - bs[sq][m][o - RX1];
-          G[2][m] = bs[spl][m][o] - bs[sm][m][o];
+          G[0][m] = bs[sq][m][ot + 1] - bs[sq][m][ot - 1];
+          G[1][m] = bs[sq][m][ot + RX1] - bs[sq][m][ot - RX1];
+          G[2][m] = Bp[m] - Bqm[m];
         }
-        const double(&F)[3][3] = Fprev;
         double cq[3];
         cq[0] = F[0][2] * G[1][0] + F[1][2] * G[1][1] + F[2][2] * G[1][2] -
                 (F[0][1] * G[2][0] + F[1][1] * G[2][1] + F[2][1] * G[2][2]);
@@ -331,13 +443,13 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
                 (F[0][2] * G[0][0] + F[1][2] * G[0][1] + F[2][2] * G[0][2]);
         cq[2] = F[0][1] * G[0][0] + F[1][1] * G[0][1] + F[2][1] * G[0][2] -
                 (F[0][0] * G[1][0] + F[1][0] * G[1][1] + F[2][0] * G[1][2]);
-        const double w[3] = {cq[0] * rDprev, cq[1] * rDprev, cq[2] * rDprev};
+        const double w[3] = {cq[0] * rDq, cq[1] * rDq, cq[2] * rDq};
         double J[3];
 #pragma unroll
         for (int m = 0; m < 3; m++) J[m] = F[m][0] * w[0] + F[m][1] * w[1] + F[m][2] * w[2];
-        const double fb[3] = {gamma * ubprev[0], gamma * ubprev[1], gamma * ubprev[2]};
+        const double fb[3] = {gamma * ubq[0], gamma * ubq[1], gamma * ubq[2]};
         double Jb[3], t3[3];
-        cross(Bm, fb, Jb);
+        cross(Bq, fb, Jb);
         cross(fb, J, t3);
 #pragma unroll
         for (int m = 0; m < 3; m++) Bb[m] += t3[m];
@@ -348,7 +460,7 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
         for (int m = 0; m < 3; m++)
 #pragma unroll
           for (int n2 = 0; n2 < 3; n2++) Fb[m][n2] += Jb[m] * w[n2];
-        const double cb[3] = {wb[0] * rDprev, wb[1] * rDprev, wb[2] * rDprev};
+        const double cb[3] = {wb[0] * rDq, wb[1] * rDq, wb[2] * rDq};
         rDb += wb[0] * cq[0] + wb[1] * cq[1] + wb[2] * cq[2];
         // c'_q = F'_b . G'_a - F'_a . G'_b for (a, b, q) = (1, 2, 0), (2, 0, 1), (0, 1, 2)
 #pragma unroll
@@ -362,45 +474,37 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
         }
         if constexpr (SEED) {
           double f[3];
-          cross(J, Bm, f);
+          cross(J, Bq, f);
           Db_direct += a.seed_R2 * 0.5 * g.dV * g.inv8h3 * (f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
         }
       }
       // transpose of G': Bbar(m) += sum_a Gbar'_a(m - e_a) - Gbar'_a(m + e_a)
 #pragma unroll
-      for (int m = 0; m < 3; m++) {
-        Bb[m] += gxy[gb][m][o - 1] - gxy[gb][m][o + 1];
-        Bb[m] += gxy[gb][3 + m][o - RX1] - gxy[gb][3 + m][o + RX1];
-        Bb[m] += gzm[m] - gzp[m];
-      }
-      const double(&F)[3][3] = Fprev;
+      for (int m = 0; m < 3; m++) Bb[m] += Bbxyq[m] + (gzqm[m] - gzp[m]);
       if constexpr (SEED) {
         double zeta = 1.0;
         if (bcx == BC_LINE_TIED && (gi_t == 0 || gi_t == nx - 1)) zeta *= 0.5;
         if (bcy == BC_LINE_TIED && (gj_t == 0 || gj_t == ny - 1)) zeta *= 0.5;
         if (bcz == BC_LINE_TIED && (q == 0 || q == nz - 1)) zeta *= 0.5;
         const double kappa = a.seed_EM * zeta * g.dV * g.inv8h3;
-        const double Dp = 1.0 / rDprev;
+        const double Dp = 1.0 / rDq;
 #pragma unroll
-        for (int m = 0; m < 3; m++) Bb[m] += kappa * Dp * Bm[m];
-        Db_direct += 0.5 * kappa * (Bm[0] * Bm[0] + Bm[1] * Bm[1] + Bm[2] * Bm[2]);
+        for (int m = 0; m < 3; m++) Bb[m] += kappa * Dp * Bq[m];
+        Db_direct += 0.5 * kappa * (Bq[0] * Bq[0] + Bq[1] * Bq[1] + Bq[2] * Bq[2]);
       }
       // pull-back B = F' B0'' rD
-      const double q0 = a.B0[idx], q1 = a.B0[idx + N], q2 = a.B0[idx + 2 * N];
-      const double b0v[3] = {q0, q1, q2};
       double v[3];
 #pragma unroll
-      for (int m = 0; m < 3; m++) v[m] = F[m][0] * q0 + F[m][1] * q1 + F[m][2] * q2;
+      for (int m = 0; m < 3; m++) v[m] = F[m][0] * b0q[0] + F[m][1] * b0q[1] + F[m][2] * b0q[2];
       rDb += Bb[0] * v[0] + Bb[1] * v[1] + Bb[2] * v[2];
 #pragma unroll
       for (int m = 0; m < 3; m++)
 #pragma unroll
-        for (int n2 = 0; n2 < 3; n2++) Fb[m][n2] += rDprev * Bb[m] * b0v[n2];
+        for (int n2 = 0; n2 < 3; n2++) Fb[m][n2] += rDq * Bb[m] * b0q[n2];
 #pragma unroll
-      for (int n2 = 0; n2 < 3; n2++)
-        a.B0bar[idx + n2 * N] += rDprev * (F[0][n2] * Bb[0] + F[1][n2] * Bb[1] + F[2][n2] * Bb[2]);
+      for (int n2 = 0; n2 < 3; n2++) so_B[n2] = bbr[n2] + rDq * (F[0][n2] * Bb[0] + F[1][n2] * Bb[1] + F[2][n2] * Bb[2]);
       // det: Dbar' cof(F')
-      const double Db = -rDprev * rDprev * rDb + Db_direct;
+      const double Db = -rDq * rDq * rDb + Db_direct;
       double cof[3][3];
       cof[0][0] = F[1][1] * F[2][2] - F[1][2] * F[2][1];
       cof[0][1] = F[1][2] * F[2][0] - F[1][0] * F[2][2];
@@ -414,28 +518,37 @@ __global__ __launch_bounds__(NTHREADS) void adj_field_kernel(AdjArgs a) {
 #pragma unroll
       for (int m = 0; m < 3; m++)
 #pragma unroll
-        for (int n2 = 0; n2 < 3; n2++) a.Fbar[(3 * m + n2) * N + idx] = Fb[m][n2] + Db * cof[m][n2];
+        for (int n2 = 0; n2 < 3; n2++) so_F[3 * m + n2] = Fb[m][n2] + Db * cof[m][n2];
     }
-    // rotate the carried tile-point values
+    load_point(p);  // B0bar'' at the output node of the next plane step
+    store_point(q, qout);
+    __syncthreads();
+
 #pragma unroll
     for (int m = 0; m < 3; m++) {
-#pragma unroll
-      for (int n2 = 0; n2 < 3; n2++) Fprev[m][n2] = Fcur[m][n2];
-      ubprev[m] = ubcur[m];
-      gzm[m] = gzq[m];
+      Fzq[m] = Fzp[m];
+      ubq[m] = ubp[m];
+      Bqm[m] = Bq[m];
+      Bq[m] = Bp[m];
+      b0q[m] = b0p[m];
+      gzqm[m] = gzq[m];
       gzq[m] = gzp[m];
+      Bbxyq[m] = Bbxyp[m];
     }
-    rDprev = rDcur;
+    rDq = rDp;
   }
 }
 
-// ybar(p) = D^T Fbar': each column a of Fbar' is pulled back along axis a with the transposed
+// ybar = D^T Fbar': each column a of Fbar' is pulled back along axis a with the transposed
 // difference rows (central: +1 at n+e_a, -1 at n-e_a; one-sided ends: (-3, 4, -1) and (3, -4, 1)).
-// mode 0: ybar_out = D^T Fbar';  mode 1: xbar += D^T Fbar' + sum_{t=2..6} ybar_t;  mode 2: xbar = D^T Fbar'
-__global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a, int mode) {
+// mode 0 (stage t >= 2): ybar_t = D^T Fbar' -> ybar_out, and the cotangent of k_{t-1},
+//   dt (b5_{t-1} xbar + sum_{t' >= t} a_{t',t-1} ybar_{t'}) -> ubar_out;
+// mode 1 (stage 1): xbar += D^T Fbar' + sum_{t=2..6} ybar_t;  mode 2 (seed): xbar = D^T Fbar'
+__global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a, int mode, int stage) {
   const Geometry& g = a.g;
   const long long N = g.N;
   const int nx = g.n[0], ny = g.n[1];
+  const double dt = (mode == 0) ? *a.dt : 0.0;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(p % nx), j = (int)((p / nx) % ny), k = (int)(p / ((long long)nx * ny));
     const int id[3] = {i, j, k};
@@ -465,8 +578,14 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(AdjArgs a, int mode) {
       }
     }
     if (mode == 0) {
+      const int s = stage - 1;  // the stage whose k's cotangent is assembled
 #pragma unroll
-      for (int r = 0; r < 3; r++) a.ybar_out[p + r * N] = yb[r];
+      for (int r = 0; r < 3; r++) {
+        a.ybar_out[p + r * N] = yb[r];
+        double v = CK::b5[s - 1] * a.xbar[p + r * N] + CK::a[stage - 1][s - 1] * yb[r];
+        for (int t = stage + 1; t <= 6; t++) v += CK::a[t - 1][s - 1] * a.ybar[t][p + r * N];
+        a.ubar_out[p + r * N] = dt * v;
+      }
     } else if (mode == 1) {
 #pragma unroll
       for (int r = 0; r < 3; r++) {
@@ -533,8 +652,8 @@ hipError_t launch_adj_field(int s, bool seed, const AdjArgs& a, hipStream_t st) 
   return xyp ? launch_field_x<true>(s, seed, a, st) : launch_field_x<false>(s, seed, a, st);
 }
 
-hipError_t launch_adj_gather(const AdjArgs& a, int mode, hipStream_t st) {
-  hipLaunchKernelGGL(adj_gather_kernel, dim3(grid_for(a.g.N)), dim3(256), 0, st, a, mode);
+hipError_t launch_adj_gather(const AdjArgs& a, int mode, int stage, hipStream_t st) {
+  hipLaunchKernelGGL(adj_gather_kernel, dim3(grid_for(a.g.N)), dim3(256), 0, st, a, mode, stage);
   return hipGetLastError();
 }
 

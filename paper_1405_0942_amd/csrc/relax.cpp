@@ -28,7 +28,7 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 struct Layout {
   size_t ctl, x0, x1, k[5], y[2], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
   // reverse mode (record = 1): segment positions and stage vectors, cotangents, seed
-  size_t ctl2, seg_x, seg_k, Fbar, xbar, ybar, B0bar, useed;
+  size_t ctl2, seg_x, seg_k, seg_y, Fbar, xbar, ybar, ubar, B0bar, useed;
   int ckpt_slots;
 };
 
@@ -55,6 +55,8 @@ struct Ctx {
   Control* d_ctl2 = nullptr;
   double* d_seg_x = nullptr;
   double* d_seg_k = nullptr;
+  double* d_seg_y = nullptr;
+  double* d_ubar = nullptr;
   double* d_Fbar = nullptr;
   double* d_xbar = nullptr;
   double* d_ybar = nullptr;
@@ -164,7 +166,7 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   L.out = take(16 * sizeof(double));
   L.ckpt_slots = 0;
   L.dtrec = L.ckpt = 0;
-  L.ctl2 = L.seg_x = L.seg_k = L.Fbar = L.xbar = L.ybar = L.B0bar = L.useed = 0;
+  L.ctl2 = L.seg_x = L.seg_k = L.seg_y = L.Fbar = L.xbar = L.ybar = L.ubar = L.B0bar = L.useed = 0;
   if (c->record && K_record > 0) {
     const size_t cpe = (size_t)c->checkpoint_every;
     L.dtrec = take((size_t)K_record * sizeof(double));
@@ -173,9 +175,11 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
     L.ctl2 = take(sizeof(Control));
     L.seg_x = take((cpe + 1) * N3 * sizeof(double));
     L.seg_k = take(cpe * 5 * N3 * sizeof(double));
+    L.seg_y = take(cpe * 4 * N3 * sizeof(double));
     L.Fbar = take(3 * N3 * sizeof(double));
     L.xbar = take(N3 * sizeof(double));
     L.ybar = take(5 * N3 * sizeof(double));
+    L.ubar = take(N3 * sizeof(double));
     L.B0bar = take(N3 * sizeof(double));
     L.useed = take(N3 * sizeof(double));
   }
@@ -205,8 +209,7 @@ SweepArgs sweep_args(Ctx* c) {
   a.xout[1] = c->d_x[1];
   for (int s = 0; s < 5; s++) a.k[s] = c->d_k[s];
   a.k[5] = nullptr;
-  a.y[0] = c->d_y[0];
-  a.y[1] = c->d_y[1];
+  for (int t = 0; t < 4; t++) a.y[t] = c->d_y[(t + 1) & 1];  // y_3 .. y_6 alternate between two buffers
   a.B0 = c->d_B0;
   a.ctl = c->d_ctl;
   a.part = c->d_part;
@@ -333,6 +336,8 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
     c->d_ctl2 = reinterpret_cast<Control*>(c->base + L.ctl2);
     c->d_seg_x = reinterpret_cast<double*>(c->base + L.seg_x);
     c->d_seg_k = reinterpret_cast<double*>(c->base + L.seg_k);
+    c->d_seg_y = reinterpret_cast<double*>(c->base + L.seg_y);
+    c->d_ubar = reinterpret_cast<double*>(c->base + L.ubar);
     c->d_Fbar = reinterpret_cast<double*>(c->base + L.Fbar);
     c->d_xbar = reinterpret_cast<double*>(c->base + L.xbar);
     c->d_ybar = reinterpret_cast<double*>(c->base + L.ybar);
@@ -496,6 +501,8 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
   a.seed_R2 = seed_R2;
   a.xbar = c->d_xbar;
   for (int t = 2; t <= 6; t++) a.ybar[t] = c->d_ybar + (size_t)(t - 2) * N3;
+  a.ubar = c->d_ubar;
+  a.ubar_out = c->d_ubar;
   HIP_TRY(c, launch_fill(c->d_B0bar, (long long)N3, 0.0, st));
 
   // seed: cotangents of E_M(x_K) and R2(x_K)
@@ -509,7 +516,7 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
   a.x = c->d_x[c->cur];
   HIP_TRY(c, launch_adj_field(1, true, a, st));
   a.xbar_out = c->d_xbar;
-  HIP_TRY(c, launch_adj_gather(a, 2, st));
+  HIP_TRY(c, launch_adj_gather(a, 2, 1, st));
   a.useed = nullptr;
 
   // reverse over the recorded steps, one checkpoint segment at a time
@@ -525,27 +532,30 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
     const int len = (int)(s1 - s0);
     HIP_TRY(c, hipMemcpyAsync(c->d_seg_x, c->d_ckpt + (size_t)seg * N3, N3 * sizeof(double),
                               hipMemcpyDeviceToDevice, st));
-    for (int j = 0; j < len; j++) {  // forward recompute, keeping x_n and k_1..k_5 of every step
+    // forward recompute, keeping x_n, k_1..k_5 and y_3..y_6 of every step
+    for (int j = 0; j < len; j++) {
       HIP_TRY(c, launch_seg_step(c->d_ctl2, c->d_dtrec, s0 + j, st));
       fw.x[0] = c->d_seg_x + (size_t)j * N3;
       fw.x[1] = c->d_seg_x + (size_t)(j + 1) * N3;
       fw.xout[0] = c->d_seg_x + (size_t)j * N3;
       fw.xout[1] = c->d_seg_x + (size_t)(j + 1) * N3;
       for (int s = 0; s < 5; s++) fw.k[s] = c->d_seg_k + ((size_t)j * 5 + s) * N3;
+      for (int t = 0; t < 4; t++) fw.y[t] = c->d_seg_y + ((size_t)j * 4 + t) * N3;
       for (int s = 1; s <= 6; s++) HIP_TRY(c, launch_stage(s, false, fw, st));
     }
     for (int j = len - 1; j >= 0; j--) {
       a.x = c->d_seg_x + (size_t)j * N3;
       for (int s = 0; s < 5; s++) a.k[s] = c->d_seg_k + ((size_t)j * 5 + s) * N3;
+      for (int t = 0; t < 4; t++) a.y[t] = c->d_seg_y + ((size_t)j * 4 + t) * N3;
       a.dt = c->d_dtrec + s0 + j;
       for (int s = 6; s >= 1; s--) {
         HIP_TRY(c, launch_adj_field(s, false, a, st));
         if (s >= 2) {
           a.ybar_out = c->d_ybar + (size_t)(s - 2) * N3;
-          HIP_TRY(c, launch_adj_gather(a, 0, st));
+          HIP_TRY(c, launch_adj_gather(a, 0, s, st));
         } else {
           a.xbar_out = c->d_xbar;
-          HIP_TRY(c, launch_adj_gather(a, 1, st));
+          HIP_TRY(c, launch_adj_gather(a, 1, 1, st));
         }
       }
     }

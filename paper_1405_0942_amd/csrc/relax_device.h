@@ -65,7 +65,7 @@ struct SweepArgs {
   const double* x[2];  // position buffers (x_n is x[ctl->cur])
   double* xout[2];     // same buffers, writable (stage 6 writes x[1 - cur])
   void* k[6];          // stage vectors k1..k5 (double, or float in mixed mode)
-  double* y[2];        // stage inputs y_3..y_6 (y_t in y[t % 2]), written by stages 2..5
+  double* y[4];        // stage inputs y_3..y_6 (y_t in y[t - 3]), written by stages 2..5
   const void* B0;      // initial field (double, or float in mixed mode)
   Control* ctl;
   double* part;        // [nblocks][NPART] reduction partials of stage 1 / diagnostics
@@ -83,14 +83,17 @@ struct AdjArgs {
   Geometry g;
   const double* x;        // x_n of the step (or x_K for the seed sweep)
   const double* k[5];     // k_1..k_5 of the step
+  const double* y[4];     // stage inputs y_3..y_6 of the step
   const double* dt;       // device pointer to the step's dt
   const double* B0;       // B0'' (prescaled, FP64)
   const double* xbar;     // cotangent of x_{n+1}
   const double* ybar[7];  // ybar_t for t = 2..6 (index t)
+  const double* ubar;     // cotangent of k_s for the field sweep of stage s < 6 (gather output)
   const double* useed;    // seed sweep: cotangent of u (may be null)
   double* Fbar;           // [9][N] cotangent of F' (row-major 3x3 per node, component-major)
   double* B0bar;          // [3][N] accumulated cotangent of B0''
-  double* ybar_out;       // gather mode 0 output
+  double* ybar_out;       // gather mode 0 output: ybar_t
+  double* ubar_out;       // gather mode 0 output: cotangent of k_{t-1}
   double* xbar_out;       // gather modes 1, 2 output
   double gamma, seed_EM, seed_R2;
 };
@@ -123,7 +126,7 @@ hipError_t launch_begin_chunk(Control* ctl, int target, hipStream_t st);
 hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t st);
 hipError_t launch_prescale(double* B0, long long N, const double scale[3], hipStream_t st);
 hipError_t launch_adj_field(int s, bool seed, const AdjArgs& a, hipStream_t st);
-hipError_t launch_adj_gather(const AdjArgs& a, int mode, hipStream_t st);
+hipError_t launch_adj_gather(const AdjArgs& a, int mode, int stage, hipStream_t st);
 hipError_t launch_fill(double* v, long long n, double val, hipStream_t st);
 hipError_t launch_seg_step(Control* c2, const double* dt_record, long long n, hipStream_t st);
 hipError_t launch_max_norm2(const double* v, long long N, double* out, hipStream_t st);

@@ -218,7 +218,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   __shared__ double red[NTHREADS / 64][NPART];
 
   const double* __restrict__ xn = a.x[cur];
-  const double* __restrict__ wsrc = (S <= 2) ? xn : a.y[S & 1];  // the stencilled vector
+  const double* __restrict__ wsrc = (S <= 2) ? xn : a.y[S > 2 ? S - 3 : 0];  // the stencilled vector
   const T* __restrict__ k1p = static_cast<const T*>(a.k[0]);
   const T* __restrict__ b0p = static_cast<const T*>(a.B0);
 
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     } else if constexpr (!LAST) {
       const unsigned eo = on ? out_e : IE;
       T* dk = static_cast<T*>(a.k[S - 1]);
-      double* dy = a.y[(S + 1) & 1];
+      double* dy = a.y[S >= 2 ? S - 2 : 0];
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), eo, so_k[m]);
 #pragma unroll

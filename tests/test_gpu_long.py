@@ -1,0 +1,115 @@
+"""Long runs of the braid workloads: FP64 against the oracle (64x64x192), and FP32-mixed
+against FP64 (128x128x384).
+
+* Braid 64x64x192, FP64, adaptive: the oracle replays the GPU's accepted dt sequence for
+  the first 300 steps (E_M, xi and the displacement compared step by step); the GPU then
+  runs on to 4000 steps, and the oracle's diagnostics of the GPU's final positions must
+  match the GPU's own FP64 diagnostics sweep of them.  (Run on, this discretization of the
+  braid develops a grid-scale instability: xi bottoms out near 1.9e-2 around step 4250,
+  then grows while E_M turns upward and det F collapses, and the step size falls below
+  1e-12 near step 5440, t = 35.5.  The oracle, restarted from the GPU's positions at steps
+  4800 and 5000 with the GPU's dt sequence, follows the same path to 1e-15 in E_M.)
+* Braid 128x128x384, FP64 and FP32-mixed, 5000 steps at the same fixed dt: E_M of every
+  step and the final FP64-evaluated xi and R2 of the mixed run within 1e-5 relative of the
+  FP64 run (the mixed mode keeps positions in FP64 and evaluates the final diagnostics with
+  the FP64 sweep); the first 10 mixed steps also against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import banner, context, host, nrel, rel
+
+import paper_1405_0942_amd as R
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def test_braid_64_fp64_long_run_vs_oracle():
+    w = W.braid(64, 192)
+    g = w.grid
+    tau_B2 = oracle.null_threshold(w.B0)
+    K_cmp, K_total = 300, 4000
+    banner(f"braid 64x64x192 FP64 adaptive: {K_cmp} steps vs oracle replay, then to {K_total}")
+    with context(g, w.x0, w.B0, dt0=w.dt0, tol=w.tol) as r:
+        diag = r.step(K_cmp)
+        x_cmp = host(r.state()[0])
+        rest = r.step(K_total - K_cmp)
+        xK = host(r.state()[0])
+        dK = r.diagnostics()
+    gdt = np.array([d["dt"] for d in diag])
+    ref = oracle.run(g, w.x0, w.B0, K_cmp, dt=gdt[0], mode=oracle.MODE_REPLAY, dts=gdt, tau_B2=tau_B2)
+    od = ref["diag"]
+    E = np.array([d["E_M"] for d in diag])
+    xi = np.array([d["xi"] for d in diag])
+    errE = np.abs(E - od[:, 2]).max() / E[0]
+    errxi = np.abs(xi - od[:, 3]).max() / np.abs(od[:, 3]).max()
+    errx = nrel(x_cmp - w.x0, ref["x"] - w.x0)
+    banner(f"  {K_cmp} steps: E_M {errE:.2e}, xi {errxi:.2e}, displacement {errx:.2e}; "
+           f"rejects {sum(d['rejects'] for d in diag)}")
+    assert errE < 1e-11
+    assert errxi < 1e-9
+    assert errx < 1e-9
+    # the rest of the run: energy decreases, and the final diagnostics agree with the oracle's
+    # evaluation of the GPU's final positions
+    E_all = np.concatenate([E, [d["E_M"] for d in rest]])
+    assert np.all(E_all[1:] <= E_all[:-1] * (1 + 1e-13))
+    assert dK["xi"] < 0.25 * diag[0]["xi"]
+    o = oracle.diagnostics(g, xK, w.B0, tau_B2=tau_B2)
+    banner(f"  step {K_total}: t {rest[-1]['t']:.4f}, E_M {dK['E_M']:.10g}, xi {dK['xi']:.3e}, "
+           f"R2 {dK['R2']:.3e}; oracle diagnostics rel E {rel(dK['E_M'], o['E_M']):.1e} "
+           f"xi {rel(dK['xi'], o['xi']):.1e} R2 {rel(dK['R2'], o['R2']):.1e}")
+    assert rel(dK["E_M"], o["E_M"]) < 1e-12
+    assert rel(dK["R2"], o["R2"]) < 1e-11
+    assert rel(dK["xi"], o["xi"]) < 1e-11
+    assert rel(dK["min_det"], o["min_det"]) < 1e-12
+
+
+def _probe_dt(w, steps=40):
+    """Smallest dt the adaptive FP64 run accepts over its first steps (a fixed dt below the
+    stability limit of the whole run, whose steps only grow as the field relaxes)."""
+    with context(w.grid, w.x0, w.B0, dt0=w.dt0, tol=w.tol) as r:
+        d = r.step(steps)
+    return min(x["dt"] for x in d)
+
+
+def test_braid_128_mixed_vs_fp64():
+    w = W.braid(128, 384)
+    g = w.grid
+    K = 5000
+    dt = _probe_dt(w)
+    banner(f"braid 128x128x384: FP64 and FP32-mixed, {K} steps at dt {dt:.4e}")
+    runs = {}
+    for prec in (R.RELAX_FP64, R.RELAX_FP32_MIXED):
+        with context(g, w.x0, w.B0, dt0=dt, adaptive=False, precision=prec) as r:
+            diag = r.step(K)
+            fin = r.diagnostics()
+            x = host(r.state()[0])
+        runs[prec] = (np.array([d["E_M"] for d in diag]), fin, x, diag)
+    E64, f64, x64, d64 = runs[R.RELAX_FP64]
+    E32, f32, x32, d32 = runs[R.RELAX_FP32_MIXED]
+    errE = float(np.max(np.abs(E32 - E64) / np.abs(E64)))
+    banner(f"  E_M(t) max rel {errE:.2e}; final (FP64 sweep) E_M {rel(f32['E_M'], f64['E_M']):.2e} "
+           f"xi {rel(f32['xi'], f64['xi']):.2e} ({f64['xi']:.3e} vs {f32['xi']:.3e}) "
+           f"R2 {rel(f32['R2'], f64['R2']):.2e}; displacement {nrel(x32 - w.x0, x64 - w.x0):.2e}; "
+           f"in-loop xi FP64 {d64[-1]['xi']:.3e} mixed {d32[-1]['xi']:.3e}")
+    assert errE < 1e-5
+    assert rel(f32["E_M"], f64["E_M"]) < 1e-5
+    assert rel(f32["xi"], f64["xi"]) < 1e-5
+    assert rel(f32["R2"], f64["R2"]) < 1e-5
+    # the FP64 sweep of the mixed run's final positions is the oracle's diagnostics of them
+    tau_B2 = oracle.null_threshold(w.B0)
+    o = oracle.diagnostics(g, x32, w.B0, tau_B2=tau_B2)
+    assert rel(f32["E_M"], o["E_M"]) < 1e-12
+    assert rel(f32["R2"], o["R2"]) < 1e-11
+    assert rel(f32["xi"], o["xi"]) < 1e-11
+    # the first mixed steps against the oracle
+    ref = oracle.run(g, w.x0, w.B0, 10, dt=dt, mode=oracle.MODE_FIXED, tau_B2=tau_B2)
+    errE10 = float(np.max(np.abs(E32[:10] - ref["diag"][:, 2]) / ref["diag"][:, 2]))
+    banner(f"  first 10 mixed steps vs oracle: E_M max rel {errE10:.2e}")
+    assert errE10 < 1e-5
