@@ -29,13 +29,18 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point updates/s (FP64 vs FP32-mixed) + % HBM roofline at 256^3"
 
-# algorithmic HBM bytes per node of each stage sweep, FP64 and FP32-mixed (x_n and the stage
-# inputs y_s in FP64; k_j and B0 in FP32 in mixed mode):
+# algorithmic HBM bytes per node of each stage sweep.  Both modes:
 #   stage 1: x_n, B0 -> k_1
 #   stage 2: x_n, k_1, B0, k_1 at the node -> k_2, y_3
-#   stage s = 3..5: y_s, B0, k_1..k_{s-1} at the node -> k_s, y_{s+1}
+#   stage 3: y_3, B0, k_1, k_2 at the node -> k_3, y_4
+# FP64 (every vector 24 B):
+#   stage 4: y_4, B0, k_1..k_3 at the node -> y_5 and the sums Y6, dX, E
+#   stage 5: y_5, B0, Y6 and E at the node -> y_6, E
+#   stage 6: y_6, B0, x_n, dX and E at the node -> x_{n+1}
+# FP32-mixed (x_n, y_s in FP64; k_j and B0 in FP32):
+#   stage s = 4, 5: y_s, B0, k_1..k_{s-1} at the node -> k_s, y_{s+1}
 #   stage 6: y_6, B0, x_n, k_1, k_3, k_4, k_5 at the node -> x_{n+1}
-BYTES_FP64 = [72, 144, 144, 168, 192, 192]
+BYTES_FP64 = [72, 144, 144, 216, 144, 144]
 BYTES_MIXED = [48, 96, 96, 108, 120, 132]
 
 

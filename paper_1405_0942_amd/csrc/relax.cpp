@@ -26,7 +26,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t ctl, x0, x1, k[5], y[2], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
+  size_t ctl, x0, x1, k[5], y[2], acc, B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
   // reverse mode (record = 1): segment positions and stage vectors, cotangents, seed
   size_t ctl2, seg_x, seg_k, seg_y, Fbar, xbar, ybar, ubar, B0bar, useed;
   int ckpt_slots;
@@ -43,6 +43,7 @@ struct Ctx {
   Control* d_ctl = nullptr;
   double* d_x[2] = {nullptr, nullptr};
   void* d_k[5] = {};
+  double* d_acc[3] = {nullptr, nullptr, nullptr};
   double* d_y[2] = {nullptr, nullptr};
   void* d_B0 = nullptr;
   double* d_B0_64 = nullptr;
@@ -156,8 +157,11 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   L.ctl = take(sizeof(Control));
   L.x0 = take(N3 * sizeof(double));
   L.x1 = take(N3 * sizeof(double));
-  for (int s = 0; s < 5; s++) L.k[s] = take(N3 * ts);
+  // FP64: k_1..k_3 and the partial sums of stage 4; FP32-mixed: k_1..k_5 (see stage.hip)
+  const bool mixed = (c->precision == RELAX_FP32_MIXED);
+  for (int s = 0; s < 5; s++) L.k[s] = (s < 3 || mixed) ? take(N3 * ts) : 0;
   for (int t = 0; t < 2; t++) L.y[t] = take(N3 * sizeof(double));
+  L.acc = mixed ? 0 : take(3 * N3 * sizeof(double));
   L.B0_64 = take(N3 * sizeof(double));
   L.B0 = (c->precision == RELAX_FP32_MIXED) ? take(N3 * sizeof(float)) : L.B0_64;
   L.part = take((size_t)g.nblocks * NPART * sizeof(double));
@@ -174,7 +178,7 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
     L.ckpt = take((size_t)L.ckpt_slots * N3 * sizeof(double));
     L.ctl2 = take(sizeof(Control));
     L.seg_x = take((cpe + 1) * N3 * sizeof(double));
-    L.seg_k = take(cpe * 5 * N3 * sizeof(double));
+    L.seg_k = take(cpe * 3 * N3 * sizeof(double));
     L.seg_y = take(cpe * 4 * N3 * sizeof(double));
     L.Fbar = take(3 * N3 * sizeof(double));
     L.xbar = take(N3 * sizeof(double));
@@ -208,6 +212,7 @@ SweepArgs sweep_args(Ctx* c) {
   a.xout[0] = c->d_x[0];
   a.xout[1] = c->d_x[1];
   for (int s = 0; s < 5; s++) a.k[s] = c->d_k[s];
+  for (int i = 0; i < 3; i++) a.acc[i] = c->d_acc[i];
   a.k[5] = nullptr;
   for (int t = 0; t < 4; t++) a.y[t] = c->d_y[(t + 1) & 1];  // y_3 .. y_6 alternate between two buffers
   a.B0 = c->d_B0;
@@ -322,7 +327,9 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   c->d_ctl = reinterpret_cast<Control*>(c->base + L.ctl);
   c->d_x[0] = reinterpret_cast<double*>(c->base + L.x0);
   c->d_x[1] = reinterpret_cast<double*>(c->base + L.x1);
-  for (int s = 0; s < 5; s++) c->d_k[s] = c->base + L.k[s];
+  for (int s = 0; s < 5; s++) c->d_k[s] = (s < 3 || c->mixed) ? c->base + L.k[s] : nullptr;
+  if (!c->mixed)
+    for (int i = 0; i < 3; i++) c->d_acc[i] = reinterpret_cast<double*>(c->base + L.acc) + (size_t)i * 3 * c->g.N;
   for (int t = 0; t < 2; t++) c->d_y[t] = reinterpret_cast<double*>(c->base + L.y[t]);
   c->d_B0_64 = reinterpret_cast<double*>(c->base + L.B0_64);
   c->d_B0 = c->base + L.B0;
@@ -539,13 +546,13 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
       fw.x[1] = c->d_seg_x + (size_t)(j + 1) * N3;
       fw.xout[0] = c->d_seg_x + (size_t)j * N3;
       fw.xout[1] = c->d_seg_x + (size_t)(j + 1) * N3;
-      for (int s = 0; s < 5; s++) fw.k[s] = c->d_seg_k + ((size_t)j * 5 + s) * N3;
+      for (int s = 0; s < 3; s++) fw.k[s] = c->d_seg_k + ((size_t)j * 3 + s) * N3;
       for (int t = 0; t < 4; t++) fw.y[t] = c->d_seg_y + ((size_t)j * 4 + t) * N3;
       for (int s = 1; s <= 6; s++) HIP_TRY(c, launch_stage(s, false, fw, st));
     }
     for (int j = len - 1; j >= 0; j--) {
       a.x = c->d_seg_x + (size_t)j * N3;
-      for (int s = 0; s < 5; s++) a.k[s] = c->d_seg_k + ((size_t)j * 5 + s) * N3;
+      for (int s = 0; s < 3; s++) a.k[s] = c->d_seg_k + ((size_t)j * 3 + s) * N3;
       for (int t = 0; t < 4; t++) a.y[t] = c->d_seg_y + ((size_t)j * 4 + t) * N3;
       a.dt = c->d_dtrec + s0 + j;
       for (int s = 6; s >= 1; s--) {

@@ -66,6 +66,7 @@ struct SweepArgs {
   double* xout[2];     // same buffers, writable (stage 6 writes x[1 - cur])
   void* k[6];          // stage vectors k1..k5 (double, or float in mixed mode)
   double* y[4];        // stage inputs y_3..y_6 (y_t in y[t - 3]), written by stages 2..5
+  double* acc[3];      // FP64 mode: partial sums Y6, dX, E written by stage 4 (see stage.hip)
   const void* B0;      // initial field (double, or float in mixed mode)
   Control* ctl;
   double* part;        // [nblocks][NPART] reduction partials of stage 1 / diagnostics

@@ -141,7 +141,9 @@ __device__ __forceinline__ double wave_min(double v) {
 }
 
 // the k_j a stage reads at its output node: k_1..k_{s-1} for stages 2..5 (for y_{s+1});
-// k_1, k_3, k_4, k_5 for stage 6 (the weights of k_2 in x5 and in x5 - x4 vanish)
+// k_1, k_3, k_4, k_5 for stage 6 (the weights of k_2 in x5 and in x5 - x4 vanish).  With
+// FP64 stage vectors, stage 4 instead writes the three sums the last two stages need
+// (see PART below), and stages 5 and 6 read those.
 template <int S>
 __device__ __forceinline__ constexpr int point_k(int j) {
   return (S == 6) ? (j == 0 ? 0 : j + 1) : j;
@@ -155,7 +157,17 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   constexpr bool STAGE1 = (S == 1);
   constexpr bool LAST = (S == 6);
   constexpr bool WK = (S == 2);                                // the window carries k_1 too
-  constexpr int NPK = STAGE1 ? 0 : (LAST ? 4 : S - 1);        // k_j read at the output node
+  // PART (FP64): stage 4 writes, besides y_5,
+  //   Y6 = x_n + dt sum_{j<=4} a_6j k_j   (from y_4: a stage input, rounded like y_4),
+  //   dX = dt sum_{j<=4} b5_j k_j,  E = dt sum_{j<=4} (b5_j - b4_j) k_j   (from the k_j only);
+  // stage 5 forms y_6 = Y6 + dt a_65 k_5 and adds its term to E in place; stage 6 forms
+  // x_{n+1} = x_n + (dX + dt b5_6 k_6) -- x_n plus an increment made of k_j alone, so the
+  // step keeps full relative precision however small it is -- and the error E + dt (b5_6 -
+  // b4_6) k_6.  k_4 and k_5 are never stored.  (With FP32 stage vectors the FP64 sums would
+  // move more bytes than the k_j they replace, so the mixed mode keeps k_4 and k_5.)
+  constexpr bool PART = !MIXED;
+  constexpr bool PART_IN = PART && (S == 5 || S == 6);        // reads two sums, no k_j
+  constexpr int NPK = (STAGE1 || PART_IN) ? 0 : (LAST ? 4 : S - 1);  // k_j read at the output node
   constexpr int NPKA = NPK > 0 ? NPK : 1;
   constexpr int NP2 = (RY2 * RX2 + NTHREADS - 1) / NTHREADS;  // stage-input points per thread
   constexpr int NP1 = (RY1 * RX1 + NTHREADS - 1) / NTHREADS;  // field points per thread
@@ -191,6 +203,20 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
     for (int j = 0; j < NPK; j++) cy[j] = dt * (CK::a[S][j] - CK::a[S - 1][j]);
     cys = dt * CK::a[S][S - 1];
+  }
+  // PART, stage 4: Y6 from y_4, dX and E from the k_j (cp[0..2][j] for k_1..k_3, cps[0..2]
+  // for k_4)
+  double cp[3][PART && S == 4 ? 3 : 1] = {}, cps[3] = {0.0, 0.0, 0.0};
+  if constexpr (PART && S == 4) {
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      cp[0][j] = dt * (CK::a[5][j] - CK::a[3][j]);
+      cp[1][j] = dt * CK::b5[j];
+      cp[2][j] = dt * (CK::b5[j] - CK::b4[j]);
+    }
+    cps[0] = dt * CK::a[5][3];
+    cps[1] = dt * CK::b5[3];
+    cps[2] = dt * (CK::b5[3] - CK::b4[3]);
   }
 
   const Geometry& g = a.g;
@@ -283,6 +309,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   T b0r[NP1][3];           // B0'' at the field points
   double px[LAST ? 3 : 1]; // stage 6: x_n at the output node
   T pk[NPKA][3];           // k_j at the output node
+  double ps[2][3];         // PART stages 5, 6: (Y6, E) or (dX, E) at the output node
   auto load_window = [&](int pz) {
     const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
@@ -334,6 +361,18 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     }
   };
   auto load_point = [&](int pz) {
+    if constexpr (PART_IN) {
+      const long long zo = (long long)zload(pz) * nxy;
+      if constexpr (LAST) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) px[m] = bload<double>(plane_rsrc(xn + m * N + zo, nxy), out_e);
+      }
+      const double* s0 = (S == 5) ? a.acc[0] : a.acc[1];
+#pragma unroll
+      for (int m = 0; m < 3; m++) ps[0][m] = bload<double>(plane_rsrc(s0 + m * N + zo, nxy), out_e);
+#pragma unroll
+      for (int m = 0; m < 3; m++) ps[1][m] = bload<double>(plane_rsrc(a.acc[2] + m * N + zo, nxy), out_e);
+    }
     if constexpr (NPK > 0) {
       const long long zo = (long long)zload(pz) * nxy;
       if constexpr (LAST) {
@@ -399,12 +438,28 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
 
   // ---- stores of one output plane (every lane issues them; masked-off lanes are dropped) ----
   // stage 1: k_1 (or u, in a diagnostics sweep that asks for it) and the checkpoint copy of
-  // x_n; stages 2..5: k_s and y_{s+1}; stage 6: x_{n+1}
+  // x_n; stages 2..5: k_s and y_{s+1} (PART: stage 4 y_5, Y6, X, E; stage 5 y_6, E);
+  // stage 6: x_{n+1}
   T so_k[3] = {T(0), T(0), T(0)};
   double so_y[3] = {0.0, 0.0, 0.0};
+  double so_p[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   auto store_plane = [&](int qz, bool on) {
     const long long zo = (long long)zload(qz) * nxy;
-    if constexpr (STAGE1) {
+    if constexpr (PART && (S == 4 || S == 5)) {
+      const unsigned eo = on ? out_e : IE;
+      double* dy = a.y[S - 2];
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dy + m * N + zo, nxy), eo, so_y[m]);
+      if constexpr (S == 4) {
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+          for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.acc[i] + m * N + zo, nxy), eo, so_p[i][m]);
+      } else {
+#pragma unroll
+        for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.acc[2] + m * N + zo, nxy), eo, so_p[2][m]);
+      }
+    } else if constexpr (STAGE1) {
       const bool to_u = !MIXED && diag_only && a.u_out != nullptr;
       const unsigned ek = (on && (!diag_only || to_u)) ? out_e : IE;
       const unsigned ec = (on && record_ck) ? out_e : IE;
@@ -585,6 +640,38 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int m = 0; m < 3; m++) {
           so_k[m] = diag_only ? (T)((double)u[m] * sc) : u[m];
           so_y[m] = ycq[m];
+        }
+      } else if constexpr (PART && S == 4) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          double y = ycq[m], y6 = ycq[m], xs = 0.0, es = 0.0;
+#pragma unroll
+          for (int j = 0; j < 3; j++) {
+            const double kj = pk[j][m];
+            y = fma(cy[j], kj, y);
+            y6 = fma(cp[0][j], kj, y6);
+            xs = fma(cp[1][j], kj, xs);
+            es = fma(cp[2][j], kj, es);
+          }
+          const double k4 = u[m];
+          so_y[m] = fma(cys, k4, y);
+          so_p[0][m] = fma(cps[0], k4, y6);
+          so_p[1][m] = fma(cps[1], k4, xs);
+          so_p[2][m] = fma(cps[2], k4, es);
+        }
+      } else if constexpr (PART && S == 5) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          so_y[m] = fma(dt * CK::a[5][4], (double)u[m], ps[0][m]);
+          so_p[2][m] = fma(dt * (CK::b5[4] - CK::b4[4]), (double)u[m], ps[1][m]);
+        }
+      } else if constexpr (PART && LAST) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          so_y[m] = px[m] + fma(dt * CK::b5[5], (double)u[m], ps[0][m]);
+          const double e = fma(dt * (CK::b5[5] - CK::b4[5]), (double)u[m], ps[1][m]);
+          const double err = tile_ok ? fabs(e) : 0.0;
+          acc_lam = (err > acc_lam || err != err) ? err : acc_lam;
         }
       } else if constexpr (!LAST) {
 #pragma unroll
