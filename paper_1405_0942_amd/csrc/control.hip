@@ -185,15 +185,31 @@ __global__ void prescale_kernel(double* __restrict__ v, long long N, double s0, 
   }
 }
 
-// max over nodes of |v|^2 of a [3][N] field (one workgroup; used once at set-up)
-__global__ __launch_bounds__(CT) void max_norm2_kernel(const double* __restrict__ v, long long N,
-                                                        double* __restrict__ out) {
+// max over nodes of |v|^2 of a [3][N] field, in two passes (used once at set-up): each
+// workgroup reduces a grid-stride share into part[blockIdx.x], then one workgroup reduces
+// the partials (a max, so the result does not depend on the order)
+__global__ __launch_bounds__(CT) void max_norm2_part_kernel(const double* __restrict__ v, long long N,
+                                                             double* __restrict__ part) {
   __shared__ double s[CT];
   double m = 0.0;
-  for (long long i = threadIdx.x; i < N; i += CT) {
+  for (long long i = (long long)blockIdx.x * CT + threadIdx.x; i < N; i += (long long)gridDim.x * CT) {
     const double a = v[i], b = v[i + N], c = v[i + 2 * N];
     m = max_nan(m, a * a + b * b + c * c);
   }
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = CT / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) s[threadIdx.x] = max_nan(s[threadIdx.x], s[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(CT) void max_reduce_kernel(const double* __restrict__ part, int n,
+                                                        double* __restrict__ out) {
+  __shared__ double s[CT];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += CT) m = max_nan(m, part[i]);
   s[threadIdx.x] = m;
   __syncthreads();
   for (int k = CT / 2; k > 0; k >>= 1) {
@@ -237,8 +253,14 @@ hipError_t launch_prescale(double* B0, long long N, const double scale[3], hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_max_norm2(const double* v, long long N, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(max_norm2_kernel, dim3(1), dim3(CT), 0, st, v, N, out);
+hipError_t launch_max_norm2(const double* v, long long N, double* out, double* scratch, int nscratch,
+                            hipStream_t st) {
+  long long blocks = (N + CT - 1) / CT;
+  if (blocks > nscratch) blocks = nscratch;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(max_norm2_part_kernel, dim3((unsigned)blocks), dim3(CT), 0, st, v, N, scratch);
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(CT), 0, st, scratch, (int)blocks, out);
   return hipGetLastError();
 }
 

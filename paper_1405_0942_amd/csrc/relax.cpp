@@ -369,7 +369,8 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
     return bail(RELAX_E_HIP);
   // max |B0|^2 of the caller's field (null guard of xi), then B0 -> B0'' = B0 * 4 h_b h_c for
   // the unscaled-difference form of the sweep
-  if (launch_max_norm2(c->d_B0_64, c->g.N, c->d_out, c->stream) != hipSuccess) return bail(RELAX_E_HIP);
+  if (launch_max_norm2(c->d_B0_64, c->g.N, c->d_out, c->d_part, c->g.nblocks * NPART, c->stream) != hipSuccess)
+    return bail(RELAX_E_HIP);
   if (launch_prescale(c->d_B0_64, c->g.N, c->g.b0scale, c->stream) != hipSuccess) return bail(RELAX_E_HIP);
   if (c->mixed && launch_to_float(c->d_B0_64, static_cast<float*>(c->d_B0), (long long)N3, c->stream) != hipSuccess)
     return bail(RELAX_E_HIP);

@@ -83,7 +83,7 @@ struct SweepArgs {
 struct AdjArgs {
   Geometry g;
   const double* x;        // x_n of the step (or x_K for the seed sweep)
-  const double* k[5];     // k_1..k_5 of the step
+  const double* k[5];     // k_1..k_3 of the step (k_1 is part of the stage-2 window)
   const double* y[4];     // stage inputs y_3..y_6 of the step
   const double* dt;       // device pointer to the step's dt
   const double* B0;       // B0'' (prescaled, FP64)
@@ -130,6 +130,8 @@ hipError_t launch_adj_field(int s, bool seed, const AdjArgs& a, hipStream_t st);
 hipError_t launch_adj_gather(const AdjArgs& a, int mode, int stage, hipStream_t st);
 hipError_t launch_fill(double* v, long long n, double val, hipStream_t st);
 hipError_t launch_seg_step(Control* c2, const double* dt_record, long long n, hipStream_t st);
-hipError_t launch_max_norm2(const double* v, long long N, double* out, hipStream_t st);
+// out = max over nodes of |v|^2; scratch holds nscratch >= 1 doubles of per-workgroup maxima
+hipError_t launch_max_norm2(const double* v, long long N, double* out, double* scratch, int nscratch,
+                            hipStream_t st);
 
 }  // namespace relax
