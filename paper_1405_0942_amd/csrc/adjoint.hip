@@ -71,11 +71,14 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base, unsigned nxy) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)(nxy * 8u), RSRC_WORD3);
 }
+// CP: cache policy; 2 (nt, non-temporal) on the single-use node-wise accesses, so that they
+// do not push the stencilled halo lines out of L2
+template <int CP = 0>
 __device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned e) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, 0));
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, CP));
 }
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned e, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, 2);
 }
 
 __device__ __forceinline__ int logical_block(int bid, int nb) {
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     const bool on = (pz >= z0 && pz < z1);
     const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
-    for (int m = 0; m < 3; m++) bbr[m] = bload(plane_rsrc(a.B0bar + m * N + zo, nxy), on ? out_e : IE);
+    for (int m = 0; m < 3; m++) bbr[m] = bload<2>(plane_rsrc(a.B0bar + m * N + zo, nxy), on ? out_e : IE);
   };
   double so_F[9], so_B[3];
 #pragma unroll

@@ -82,19 +82,24 @@ template <typename V>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const V* base, unsigned nxy) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<V*>(base), 0, (int)(nxy * sizeof(V)), RSRC_WORD3);
 }
-template <typename V>
+// cache policy of the single-use accesses (node-wise loads and all stores); the stencilled
+// loads keep the default so that neighbouring tiles find their halo lines in L2
+#ifndef RELAX_STREAM_CPOL
+#define RELAX_STREAM_CPOL 2  // nt: non-temporal
+#endif
+template <typename V, int CP = 0>
 __device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, unsigned e) {
   if constexpr (sizeof(V) == 8)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, CP));
   else
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e * 4u), 0, 0));
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e * 4u), 0, CP));
 }
 template <typename V>
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned e, V v) {
   if constexpr (sizeof(V) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, RELAX_STREAM_CPOL);
   else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(e * 4u), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(e * 4u), 0, RELAX_STREAM_CPOL);
 }
 
 // logical tile of this workgroup; consecutive logical tiles share an XCD (the hardware
@@ -365,25 +370,26 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       const long long zo = (long long)zload(pz) * nxy;
       if constexpr (LAST) {
 #pragma unroll
-        for (int m = 0; m < 3; m++) px[m] = bload<double>(plane_rsrc(xn + m * N + zo, nxy), out_e);
+        for (int m = 0; m < 3; m++) px[m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(xn + m * N + zo, nxy), out_e);
       }
       const double* s0 = (S == 5) ? a.acc[0] : a.acc[1];
 #pragma unroll
-      for (int m = 0; m < 3; m++) ps[0][m] = bload<double>(plane_rsrc(s0 + m * N + zo, nxy), out_e);
+      for (int m = 0; m < 3; m++) ps[0][m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(s0 + m * N + zo, nxy), out_e);
 #pragma unroll
-      for (int m = 0; m < 3; m++) ps[1][m] = bload<double>(plane_rsrc(a.acc[2] + m * N + zo, nxy), out_e);
+      for (int m = 0; m < 3; m++)
+        ps[1][m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(a.acc[2] + m * N + zo, nxy), out_e);
     }
     if constexpr (NPK > 0) {
       const long long zo = (long long)zload(pz) * nxy;
       if constexpr (LAST) {
 #pragma unroll
-        for (int m = 0; m < 3; m++) px[m] = bload<double>(plane_rsrc(xn + m * N + zo, nxy), out_e);
+        for (int m = 0; m < 3; m++) px[m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(xn + m * N + zo, nxy), out_e);
       }
 #pragma unroll
       for (int j = 0; j < NPK; j++) {
         const T* kj = static_cast<const T*>(a.k[point_k<S>(j)]);
 #pragma unroll
-        for (int m = 0; m < 3; m++) pk[j][m] = bload<T>(plane_rsrc(kj + m * N + zo, nxy), out_e);
+        for (int m = 0; m < 3; m++) pk[j][m] = bload<T, RELAX_STREAM_CPOL>(plane_rsrc(kj + m * N + zo, nxy), out_e);
       }
     }
   };
