@@ -122,23 +122,30 @@ def measured_traffic(stage, tag, workload):
     return float(v) if v is not None else None
 
 
-def copy_bandwidth(torch, mib=1024, reps=5):
-    """Device-to-device copy of `mib` MiB (the runtime's blit kernel): GB/s counting read +
-    write bytes.  Also the known-size kernel the HBM byte counters are calibrated on."""
+def stream_bandwidth(torch, mib=1024, reps=5):
+    """What plain streaming kernels reach on this device, GB/s of bytes moved: a device-to-
+    device copy of `mib` MiB (the runtime's blit kernel, also the known-size kernel the HBM
+    byte counters are calibrated on), a read-only sum and a two-read one-write add."""
     n = mib * (1 << 20) // 8
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    stop.record()
-    torch.cuda.synchronize()
-    sec = start.elapsed_time(stop) * 1e-3 / reps
-    del src, dst
-    return 2 * n * 8 / sec / 1e9
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            fn()
+        stop.record()
+        torch.cuda.synchronize()
+        return nbytes / (start.elapsed_time(stop) * 1e-3 / reps) / 1e9
+
+    out = {"copy": rate(lambda: c.copy_(a), 16 * n), "read": rate(lambda: a.sum(), 8 * n),
+           "add_2r1w": rate(lambda: torch.add(a, b, out=c), 24 * n)}
+    del a, b, c
+    return out
 
 
 def adjoint_cost(R, torch, W, steps=200, every=20):
@@ -207,8 +214,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     R.lib()  # fail loudly if the HIP library is missing
-    copy_gbs = copy_bandwidth(torch)
-    log(f"device copy {copy_gbs:.0f} GB/s (read + write)")
+    stream = stream_bandwidth(torch)
+    copy_gbs = stream["copy"]
+    log("device streaming GB/s: " + ", ".join(f"{k} {v:.0f}" for k, v in stream.items()))
     log(f"building inputs abc_{args.n}^3")
     w = W.abc_box(args.n)
     res = {}
@@ -240,6 +248,7 @@ def main():
         "roofline": m["roofline"],
         "kernels": m["kernels"],
         "copy_GBs": copy_gbs,
+        "stream_GBs": stream,
     }
     if main_key == "fp64" and "mixed" in res:
         mm = res["mixed"]

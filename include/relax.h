@@ -65,6 +65,11 @@ typedef struct {
                            for relax_backward */
   int checkpoint_every; /* checkpoint interval c (>= 1) when record = 1 */
   double xi_null_tau;   /* xi skips nodes with |B|^2 <= xi_null_tau * max |B0|^2 (e.g. 1e-12) */
+  double safety;        /* (0, 1]: factor on the new step of the rule of Sec. 2.4 (rejected and
+                           grown steps).  1 is the rule as the paper prints it; there a
+                           stability-limited run near equilibrium, where Lambda barely depends
+                           on dt, can retry a rejected step with nearly the same dt for a very
+                           long time.  0.9 (the Numerical Recipes value) avoids that. */
 } relax_config;
 
 /* Per accepted step, evaluated at the state the step starts from (pre-step). */
@@ -107,6 +112,13 @@ int relax_diagnostics(void* ctx, relax_diag* out);
  * context) into d_u_out (device, [3][nz][ny][nx], overwritten; zero on line-tied faces).
  * Blocks until done. */
 int relax_velocity(void* ctx, double* d_u_out);
+
+/* The pulled-back field B = F B0 / det F (Sec. 2.1, eq. "B transformation") and the mimetic
+ * current J (Sec. 2.2) of the current positions, evaluated in FP64 (also for a mixed-precision
+ * context) into d_B_out and d_J_out (device, [3][nz][ny][nx], overwritten).  J is zero on
+ * line-tied faces, where the loops of Sec. 2.2 are not closed.  Either pointer may be NULL.
+ * Blocks until done. */
+int relax_fields(void* ctx, double* d_B_out, double* d_J_out);
 
 /* Reverse-mode gradient through the recorded fixed-dt trajectory (record = 1):
  * d(seed_EM * E_M(x_K) + seed_R2 * R2(x_K)) / d(x0, B0), where x_K is the current state

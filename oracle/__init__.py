@@ -38,9 +38,9 @@ def lib():
     L.orc_fields.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_diagnostics.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, _dp]
     L.orc_ck_attempt.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_double, _dp, d3, C.c_void_p]
-    L.orc_controller.argtypes = [C.c_double, C.c_double, C.c_double, d3]
-    L.orc_run.argtypes = [i3, d3, i3, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int,
-                          _dp, _dp, d3, d3, C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
+    L.orc_controller.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, d3]
+    L.orc_run.argtypes = [i3, d3, i3, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
+                          C.c_int, _dp, _dp, d3, d3, C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
     L.orcz_run_fixed.argtypes = [i3, d3, i3, C.c_double, C.c_int, _dp, _zp, _zp, C.c_void_p, C.c_void_p]
     L.orc_rhs_sampled.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_long,
                                   np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS"), _dp]
@@ -128,10 +128,10 @@ def tableau():
     return A.reshape(6, 6), b5, b4
 
 
-def controller(dt, Lambda, tol):
+def controller(dt, Lambda, tol, safety=1.0):
     """Step-size rule: (accepted, dt_next)."""
     out = C.c_double(0.0)
-    acc = lib().orc_controller(float(dt), float(Lambda), float(tol), C.byref(out))
+    acc = lib().orc_controller(float(dt), float(Lambda), float(tol), float(safety), C.byref(out))
     return bool(acc), out.value
 
 
@@ -139,7 +139,7 @@ MODE_FIXED, MODE_ADAPTIVE, MODE_REPLAY = 0, 1, 2
 
 
 def run(grid, x0, B0, K, dt, mode=MODE_ADAPTIVE, tol=1e-7, dt_min=1e-12, t=0.0, tau_B2=0.0, gamma=1.0,
-        dts=None, raise_on_error=True):
+        dts=None, raise_on_error=True, safety=1.0):
     """K accepted steps from x0.  Returns dict(x, t, dt, diag (K,8), status, done).
 
     diag columns: t, dt used, E_M, xi, R2, Lambda, min Delta, rejects (pre-step state).
@@ -150,7 +150,8 @@ def run(grid, x0, B0, K, dt, mode=MODE_ADAPTIVE, tol=1e-7, dt_min=1e-12, t=0.0, 
     diag = np.zeros((max(K, 1), 8))
     done = C.c_int(0)
     dts_arr = None if dts is None else _f64(dts)
-    rc = lib().orc_run(*_g(grid), gamma, float(tau_B2), int(mode), float(tol), float(dt_min), int(K), x, B0,
+    rc = lib().orc_run(*_g(grid), gamma, float(tau_B2), int(mode), float(tol), float(safety), float(dt_min), int(K),
+                       x, B0,
                        C.byref(tt), C.byref(dd), _ptr(dts_arr), _ptr(diag), C.byref(done))
     if raise_on_error and rc != OK:
         raise OracleError(rc)

@@ -520,14 +520,16 @@ void orc_tableau(double A[36], double b5[6], double b4[6]) {
 }
 
 /* Step-size rule (Sec. 2.4, eq. "time stepping"):
- *   dt' = dt |Lambda0 / Lambda|^{0.2};
+ *   dt' = safety dt |Lambda0 / Lambda|^{0.2};
  *   Lambda > Lambda0        -> reject, redo with dt'
  *   Lambda < Lambda0 / 2    -> accept, continue with dt'
  *   otherwise               -> accept, keep dt
- * Lambda == 0 grows the step by 5x (reading R9).
+ * Lambda == 0 grows the step by 5x (reading R9).  safety = 1 is the rule as the paper prints
+ * it; a factor below 1 (as in the Numerical Recipes stepper the paper cites for Lambda) makes
+ * repeated rejects shrink dt geometrically where Lambda barely depends on dt.
  * Returns 1 for accept, 0 for reject; *dt_next receives the next dt. */
-int orc_controller(double dt, double Lambda, double tol, double *dt_next) {
-  double dtp = (Lambda > 0.0) ? dt * pow(fabs(tol / Lambda), 0.2) : 5.0 * dt;
+int orc_controller(double dt, double Lambda, double tol, double safety, double *dt_next) {
+  double dtp = (Lambda > 0.0) ? safety * dt * pow(fabs(tol / Lambda), 0.2) : 5.0 * dt;
   if (Lambda > tol) {
     *dt_next = dtp;
     return 0;
@@ -544,7 +546,7 @@ int orc_controller(double dt, double Lambda, double tol, double *dt_next) {
  * Returns a status; *done receives the number of steps completed.
  */
 int orc_run(const int n[3], const double h[3], const int bc[3], double gamma, double tau_B2, int mode,
-            double tol, double dt_min, int K, double *x, const double *B0, double *t, double *dt,
+            double tol, double safety, double dt_min, int K, double *x, const double *B0, double *t, double *dt,
             const double *dts_in, double *diag, int *done) {
   grid_t g;
   work_t w;
@@ -579,7 +581,7 @@ int orc_run(const int n[3], const double h[3], const int bc[3], double gamma, do
       }
       if (isnan(Lam) || isinf(Lam)) { rc = ORC_E_NAN; break; }
       if (mode != 1) { dt_next = dt_used; break; }
-      if (orc_controller(dt_used, Lam, tol, &dt_next)) break;
+      if (orc_controller(dt_used, Lam, tol, safety, &dt_next)) break;
       rejects += 1;
       if (dt_next < dt_min) { rc = ORC_E_DT; break; }
       *dt = dt_next;

@@ -25,7 +25,7 @@ RELAX_FP64, RELAX_FP32_MIXED = 0, 1
 
 # every symbol include/relax.h declares
 EXPORTS = ("relax_workspace_bytes", "relax_init", "relax_step", "relax_diagnostics", "relax_velocity",
-           "relax_backward",
+           "relax_fields", "relax_backward",
            "relax_get_state", "relax_set_state", "relax_profile", "relax_strerror", "relax_last_error",
            "relax_destroy")
 
@@ -47,7 +47,7 @@ class relax_config(C.Structure):
     _fields_ = [("n", C.c_int * 3), ("h", C.c_double * 3), ("bc", C.c_int * 3), ("precision", C.c_int),
                 ("gamma", C.c_double), ("dt0", C.c_double), ("dt_min", C.c_double), ("tol", C.c_double),
                 ("adaptive", C.c_int), ("record", C.c_int), ("checkpoint_every", C.c_int),
-                ("xi_null_tau", C.c_double)]
+                ("xi_null_tau", C.c_double), ("safety", C.c_double)]
 
 
 class relax_diag(C.Structure):
@@ -76,6 +76,7 @@ def lib():
     L.relax_step.argtypes = [vp, C.c_int, C.POINTER(relax_diag), C.POINTER(C.c_int)]
     L.relax_diagnostics.argtypes = [vp, C.POINTER(relax_diag)]
     L.relax_velocity.argtypes = [vp, vp]
+    L.relax_fields.argtypes = [vp, vp, vp]
     L.relax_backward.argtypes = [vp, C.c_double, C.c_double, vp, vp]
     L.relax_get_state.argtypes = [vp, vp, dp, dp]
     L.relax_set_state.argtypes = [vp, vp, C.c_double, C.c_double]
@@ -87,7 +88,7 @@ def lib():
     L.relax_last_error.restype = C.c_char_p
     L.relax_destroy.argtypes = [vp]
     L.relax_destroy.restype = None
-    for name in ("relax_init", "relax_step", "relax_diagnostics", "relax_velocity", "relax_backward",
+    for name in ("relax_init", "relax_step", "relax_diagnostics", "relax_velocity", "relax_fields", "relax_backward",
                  "relax_get_state",
                  "relax_set_state"):
         getattr(L, name).restype = C.c_int
@@ -123,6 +124,10 @@ def relax_diagnostics(ctx):
 
 def relax_velocity(ctx, d_u_out):
     return lib().relax_velocity(ctx, C.c_void_p(d_u_out))
+
+
+def relax_fields(ctx, d_B_out, d_J_out):
+    return lib().relax_fields(ctx, C.c_void_p(d_B_out), C.c_void_p(d_J_out))
 
 
 def relax_backward(ctx, seed_EM, seed_R2, d_grad_x0, d_grad_B0):
@@ -168,7 +173,7 @@ DIAG_FIELDS = ("t", "dt", "E_M", "xi", "R2", "Lambda", "min_det", "rejects")
 
 
 def make_config(grid, precision=RELAX_FP64, gamma=1.0, dt0=1e-3, dt_min=1e-12, tol=1e-7, adaptive=True,
-                record=False, checkpoint_every=20, xi_null_tau=1e-12) -> relax_config:
+                record=False, checkpoint_every=20, xi_null_tau=1e-12, safety=1.0) -> relax_config:
     """Build a relax_config from any grid with attributes n, h, bc."""
     c = relax_config()
     c.n[:] = [int(v) for v in grid.n]
@@ -183,6 +188,7 @@ def make_config(grid, precision=RELAX_FP64, gamma=1.0, dt0=1e-3, dt_min=1e-12, t
     c.record = 1 if record else 0
     c.checkpoint_every = int(checkpoint_every)
     c.xi_null_tau = float(xi_null_tau)
+    c.safety = float(safety)
     return c
 
 
@@ -243,6 +249,15 @@ class Relaxation:
         u = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         self._check(relax_velocity(self.ctx, u.data_ptr()), "relax_velocity")
         return u
+
+    def fields(self):
+        """(B, J) of the current positions (FP64; J is zero on line-tied faces), as new device
+        tensors."""
+        import torch
+        B = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        J = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        self._check(relax_fields(self.ctx, B.data_ptr(), J.data_ptr()), "relax_fields")
+        return B, J
 
     def state(self):
         """(x as a new device tensor, t, dt)"""

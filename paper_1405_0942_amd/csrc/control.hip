@@ -92,7 +92,7 @@ __global__ __launch_bounds__(CT) void control_kernel(Control* ctl, const double*
   double dt_next = dt;
   bool accept = true;
   if (c.adaptive) {
-    const double dtp = (lam > 0.0) ? dt * pow(fabs(c.tol / lam), 0.2) : 5.0 * dt;
+    const double dtp = (lam > 0.0) ? c.safety * dt * pow(fabs(c.tol / lam), 0.2) : 5.0 * dt;
     if (lam > c.tol) {
       accept = false;
       dt_next = dtp;

@@ -102,6 +102,7 @@ bool valid_config(const relax_config* c) {
   if (c->precision != RELAX_FP64 && c->precision != RELAX_FP32_MIXED) return false;
   if (!std::isfinite(c->gamma) || !(c->dt0 > 0.0) || !std::isfinite(c->dt0)) return false;
   if (!(c->dt_min >= 0.0) || !(c->tol > 0.0) || !(c->xi_null_tau >= 0.0)) return false;
+  if (!(c->safety > 0.0 && c->safety <= 1.0)) return false;
   if (c->adaptive != 0 && c->adaptive != 1) return false;
   if (c->record != 0 && c->record != 1) return false;
   if (c->record && c->checkpoint_every < 1) return false;
@@ -221,7 +222,6 @@ SweepArgs sweep_args(Ctx* c) {
   a.lam_part = c->d_lam;
   a.ckpt = c->d_ckpt;
   a.ckpt_slots = c->L.ckpt_slots;
-  a.diag_only = 0;
   a.diag_buf = 0;
   a.u_out = nullptr;
   a.u_det_scale = 0.0;
@@ -229,14 +229,16 @@ SweepArgs sweep_args(Ctx* c) {
 }
 
 // FP64 diagnostics sweep of x[buf] into d_out[0..4] = {E, R2, xi, min det, nulls}; host copy.
-// If u_out is not null it also receives the velocity u(x[buf]).
-int diagnostics_sweep(Ctx* c, int buf, double out[5], double* u_out = nullptr, double u_det_scale = 0.0) {
+// Non-null u_out, B_out, J_out also receive u, B and J of x[buf].
+int diagnostics_sweep(Ctx* c, int buf, double out[5], double* u_out = nullptr, double u_det_scale = 0.0,
+                      double* B_out = nullptr, double* J_out = nullptr) {
   SweepArgs a = sweep_args(c);
   a.B0 = c->d_B0_64;
-  a.diag_only = 1;
   a.diag_buf = buf;
   a.u_out = u_out;
   a.u_det_scale = u_det_scale;
+  a.B_out = B_out;
+  a.J_out = J_out;
   HIP_TRY(c, launch_diagnostics(a, c->stream));
   HIP_TRY(c, launch_diag_finish(c->d_part, c->g.nblocks, c->g.dV, c->d_out, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->h_ring, c->d_out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -385,6 +387,7 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   k.t = 0.0;
   k.dt = cfg->dt0;
   k.tol = cfg->tol;
+  k.safety = cfg->safety;
   k.dt_min = cfg->dt_min;
   k.gamma = cfg->gamma;
   k.tau_B2 = cfg->xi_null_tau * maxB2;
@@ -481,6 +484,16 @@ int relax_velocity(void* ctx, double* d_u_out) {
   if (rc) return rc;
   double d[5];
   return diagnostics_sweep(c, c->cur, d, d_u_out);
+}
+
+int relax_fields(void* ctx, double* d_B_out, double* d_J_out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return RELAX_E_ARG;
+  if (c->status != RELAX_OK) return RELAX_E_STATE;
+  int rc = sync_ctl(c);
+  if (rc) return rc;
+  double d[5];
+  return diagnostics_sweep(c, c->cur, d, nullptr, 0.0, d_B_out, d_J_out);
 }
 
 int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0, double* d_grad_B0) {

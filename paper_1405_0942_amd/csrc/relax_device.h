@@ -42,6 +42,7 @@ struct Geometry {
 struct Control {
   double t, dt;              // time and step to try next
   double tol, dt_min;        // Lambda_0, breakdown threshold
+  double safety;             // factor on the new step of the step-size rule
   double gamma, tau_B2;      // friction coefficient, xi null-guard threshold on |B|^2
   double dV;                 // hx hy hz
   double E, xi, R2, min_det, nulls;  // diagnostics of the state x_n the current step starts from
@@ -73,10 +74,11 @@ struct SweepArgs {
   double* lam_part;    // [nblocks] Lambda partials of stage 6
   double* ckpt;        // checkpoint store [slots][3N] (record mode), may be null
   int ckpt_slots;
-  int diag_only;       // 1: diagnostics sweep of x[diag_buf] (no gating, no k written)
-  int diag_buf;
+  int diag_buf;        // diagnostics sweep (launch_diagnostics) of x[diag_buf]
   double* u_out;       // diagnostics sweep only: if not null, receives u(x) [3][N] (FP64)
   double u_det_scale;  // diagnostics sweep only: if not 0, u_out holds u * det F * u_det_scale
+  double* B_out;       // diagnostics sweep only: if not null, receives B(x) [3][N]
+  double* J_out;       // diagnostics sweep only: if not null, receives J(x) [3][N] (0 on line-tied faces)
 };
 
 // Arguments of the reverse-mode sweeps (adjoint.hip).  FP64 throughout.
@@ -119,7 +121,7 @@ struct CK {
 // ------------------------------------------------------------------------------------------
 // stage s in 1..6; mixed selects float k / B0 storage
 hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st);
-hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st);  // FP64 sweep, diag_only
+hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st);  // FP64 sweep of x[diag_buf]
 hipError_t launch_control(Control* ctl, const double* part, const double* lam_part, int nblocks,
                           double* ring, double* dt_record, hipStream_t st);
 hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out5, hipStream_t st);

@@ -155,8 +155,10 @@ __device__ __forceinline__ constexpr int point_k(int j) {
 }
 
 // S: stage 1..6.  MIXED: k and B0 in FP32 and the stencil past F' in FP32.  XYP: x and y
-// both periodic (no line-tied rows in x and y).
-template <int S, bool MIXED, bool XYP>
+// both periodic (no line-tied rows in x and y).  DIAG (stage 1, FP64): the diagnostics sweep
+// of x[diag_buf]: no step gating and no k_1; writes u (optionally scaled by det F), B and J
+// where the caller asked for them.
+template <int S, bool MIXED, bool XYP, bool DIAG = false>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(SweepArgs a) {
   using T = typename std::conditional<MIXED, float, double>::type;
   constexpr bool STAGE1 = (S == 1);
@@ -178,7 +180,8 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   constexpr int NP1 = (RY1 * RX1 + NTHREADS - 1) / NTHREADS;  // field points per thread
 
   Control* ctl = a.ctl;
-  const bool diag_only = (a.diag_only != 0);
+  static_assert(!DIAG || (S == 1 && !MIXED), "the diagnostics sweep is the FP64 stage-1 sweep");
+  constexpr bool diag_only = DIAG;
   int cur;
   double dt = 0.0;
   bool record_ck = false;
@@ -448,7 +451,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   // stage 6: x_{n+1}
   T so_k[3] = {T(0), T(0), T(0)};
   double so_y[3] = {0.0, 0.0, 0.0};
-  double so_p[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  double so_p[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};  // PART sums; DIAG: B, J
   auto store_plane = [&](int qz, bool on) {
     const long long zo = (long long)zload(qz) * nxy;
     if constexpr (PART && (S == 4 || S == 5)) {
@@ -465,11 +468,24 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
         for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.acc[2] + m * N + zo, nxy), eo, so_p[2][m]);
       }
+    } else if constexpr (DIAG) {
+      // each output goes to the caller's array, or (masked) to x[diag_buf], never written
+      double* fb = const_cast<double*>(a.x[cur]);
+      double* du = a.u_out ? a.u_out : fb;
+      double* dB = a.B_out ? a.B_out : fb;
+      double* dJ = a.J_out ? a.J_out : fb;
+      const unsigned eu = (on && a.u_out) ? out_e : IE, eB = (on && a.B_out) ? out_e : IE;
+      const unsigned eJ = (on && a.J_out) ? out_e : IE;
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(du + m * N + zo, nxy), eu, (double)so_k[m]);
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dB + m * N + zo, nxy), eB, so_p[0][m]);
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dJ + m * N + zo, nxy), eJ, so_p[1][m]);
     } else if constexpr (STAGE1) {
-      const bool to_u = !MIXED && diag_only && a.u_out != nullptr;
-      const unsigned ek = (on && (!diag_only || to_u)) ? out_e : IE;
+      const unsigned ek = on ? out_e : IE;
       const unsigned ec = (on && record_ck) ? out_e : IE;
-      T* dk = to_u ? reinterpret_cast<T*>(a.u_out) : static_cast<T*>(a.k[0]);
+      T* dk = static_cast<T*>(a.k[0]);
       double* dc = record_ck ? a.ckpt + ck_slot * 3 * N : a.xout[0];
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), ek, so_k[m]);
@@ -592,6 +608,13 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     if (qout) {
       const bool face = face_xy || (bcz == BC_LINE_TIED && (q == 0 || q == nz - 1));
       T u[3] = {T(0), T(0), T(0)};
+      if constexpr (DIAG) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          so_p[0][m] = Bq[m];
+          so_p[1][m] = 0.0;  // J: zero on line-tied faces
+        }
+      }
       if (!face) {
         const int o = (ty + 1) * RX1 + (tx + 1);
         const int sq = q & 1;
@@ -621,6 +644,10 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         T J[3];
 #pragma unroll
         for (int m = 0; m < 3; m++) J[m] = (Fq[m][0] * cq[0] + Fq[m][1] * cq[1] + Fq[m][2] * cq[2]) * iD;
+        if constexpr (DIAG) {
+#pragma unroll
+          for (int m = 0; m < 3; m++) so_p[1][m] = J[m];
+        }
         const T f0 = J[1] * Bq[2] - J[2] * Bq[1];
         const T f1 = J[2] * Bq[0] - J[0] * Bq[2];
         const T f2 = J[0] * Bq[1] - J[1] * Bq[0];
@@ -785,9 +812,9 @@ hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st) {
 hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st) {
   const bool xyp = (a.g.bc[0] == BC_PERIODIC && a.g.bc[1] == BC_PERIODIC);
   if (xyp)
-    hipLaunchKernelGGL((stage_kernel<1, false, true>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
+    hipLaunchKernelGGL((stage_kernel<1, false, true, true>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
   else
-    hipLaunchKernelGGL((stage_kernel<1, false, false>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
+    hipLaunchKernelGGL((stage_kernel<1, false, false, true>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,50 @@
+"""IsoHelix set-up and the diagnostics of its relaxed state (Sec. 3.1, 3.2), shared by the
+oracle pin and the GPU accuracy runs.
+
+  sigma_B = sqrt(sum |B - B_relax|^2 / N), B_relax = e_z            (eq. "B relaxed"),
+  sigma_x = sqrt(sum |x - x_relax|^2 / N), x_relax the rotated grid (eq. "x analytical relaxed"),
+  eps*    = max over pairs of central-line nodes of a_r |alpha*_i - alpha*_j| / |X_i - X_j|,
+            alpha* = J.B / B^2, on X = Y = 0 (eq. "epsilon star"; the interior nodes of the line).
+"""
+import math
+import os
+
+import numpy as np
+
+import workloads as W
+
+PHI = math.pi / 4
+AR = math.sqrt(2.0)
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def grid(n):
+    """n^3 vertex grid over [-4, 4]^2 x [-10, 10], all faces line-tied (n odd: a node on X = Y = 0)."""
+    return W.make_grid((n, n, n), [(-4.0, 4.0), (-4.0, 4.0), (-10.0, 10.0)], (0, 0, 0))
+
+
+def table1():
+    """{n: (xi, eps*, sigma_B, sigma_x)} as the paper prints them (Table 1, mimetic, phi = pi/4)."""
+    out = {}
+    with open(os.path.join(HERE, "golden", "isohelix_table1_mimetic_pi4.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = line.split()
+                out[int(v[0])] = tuple(float(a) for a in v[1:])
+    return out
+
+
+def relaxed_state_errors(g, x, B, J):
+    """(sigma_B, sigma_x, eps*) of positions x with field B and current J."""
+    N = g.N
+    sB = math.sqrt(float(((B - np.array([0.0, 0.0, 1.0])[:, None, None, None]) ** 2).sum()) / N)
+    sx = math.sqrt(float(((x - W.isohelix_relaxed_map(g, PHI)) ** 2).sum()) / N)
+    nx, ny, nz = g.n
+    i, j = (nx - 1) // 2, (ny - 1) // 2
+    Bl, Jl = B[:, 1:nz - 1, j, i], J[:, 1:nz - 1, j, i]
+    alpha = (Jl * Bl).sum(axis=0) / (Bl * Bl).sum(axis=0)
+    Z = g.origin[2] + g.h[2] * np.arange(1, nz - 1)
+    dA = np.abs(alpha[:, None] - alpha[None, :])
+    dZ = np.abs(Z[:, None] - Z[None, :])
+    np.fill_diagonal(dZ, np.inf)
+    return sB, sx, float(AR * (dA / dZ).max())

@@ -75,6 +75,8 @@ def test_workspace_bytes_valid_and_invalid():
     assert R.relax_workspace_bytes(bad) == 0
     bad = _cfg(tol=-1.0)
     assert R.relax_workspace_bytes(bad) == 0
+    for sf in (0.0, 1.5, float("nan")):
+        assert R.relax_workspace_bytes(_cfg(safety=sf)) == 0
     assert R.relax_workspace_bytes(_cfg(), -1) == 0
 
 
@@ -94,6 +96,7 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
     assert R.lib().relax_step(None, 1, None, None) == R.RELAX_E_ARG
     assert R.lib().relax_diagnostics(None, None) == R.RELAX_E_ARG
     assert R.lib().relax_velocity(None, None) == R.RELAX_E_ARG
+    assert R.lib().relax_fields(None, None, None) == R.RELAX_E_ARG
     assert R.relax_last_error(None) == ""
     R.relax_destroy(None)
 
@@ -101,5 +104,5 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
 def test_config_struct_layout_matches_header():
     # n[3] int, h[3] double, bc[3] int, precision int, gamma, dt0, dt_min, tol double,
     # adaptive, record, checkpoint_every int, xi_null_tau double
-    assert ctypes.sizeof(R.relax_config) == 12 + 4 + 24 + 12 + 4 + 32 + 12 + 4 + 8
+    assert ctypes.sizeof(R.relax_config) == 12 + 4 + 24 + 12 + 4 + 32 + 12 + 4 + 8 + 8
     assert ctypes.sizeof(R.relax_diag) == 7 * 8 + 8

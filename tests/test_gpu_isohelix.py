@@ -1,0 +1,82 @@
+"""IsoHelix accuracy runs (Sec. 3.1, 3.2; the mimetic rows of Table 1, phi = pi/4, FP64).
+
+The IsoHelix field (eq. "B init analytical": B0 = 1, a_r = sqrt 2, a_z = 2) on odd vertex grids
+n^3 over [-4, 4]^2 x [-10, 10], all faces line-tied, x0 = X, relaxed with the adaptive step
+(Lambda0 = 1e-8, safety 0.9) until sigma_B and sigma_x settle (1e-3 over two chunks); B and J of the relaxed state
+come from relax_fields (checked against the oracle's fields of the same positions).
+
+sigma_B, sigma_x and eps* (definitions in isohelix_util) are compared with the values the
+paper prints in Table 1 (tests/golden/isohelix_table1_mimetic_pi4.txt) within 30 %, and
+must fall with resolution as the paper reports.  xi is not compared: it keeps falling with
+the run length and depends on Lambda0 (the paper says so, Sec. 4.1), neither of which the
+paper states; it must only show that the field relaxed.  RELAX_ISOHELIX_FULL=1 adds n = 129.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from gpu_util import banner, context, host, nrel
+from isohelix_util import PHI, grid, relaxed_state_errors, table1
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+SIZES = (17, 33, 65, 129) if os.environ.get("RELAX_ISOHELIX_FULL") == "1" else (17, 33, 65)
+
+
+def relax(n, max_steps=200_000):
+    g = grid(n)
+    B0 = W.isohelix_field(g, PHI)
+    with context(g, g.identity(), B0, dt0=1e-3, tol=1e-8, safety=0.9) as r:
+        done, chunk, hist = 0, 250, []
+        while done < max_steps:
+            d = r.step(chunk)
+            done += len(d)
+            x = host(r.state()[0])
+            Bt, Jt = r.fields()
+            B, J = host(Bt), host(Jt)
+            sB, sx, eps = relaxed_state_errors(g, x, B, J)
+            hist.append((sB, sx))
+            banner(f"  n {n}: step {done}, t {d[-1]['t']:.1f}, dt {d[-1]['dt']:.3e}, xi {d[-1]['xi']:.2e}, "
+                   f"sigma_B {sB:.3e}, sigma_x {sx:.3e}, eps* {eps:.2e}")
+            if len(hist) >= 3 and all(abs(hist[-1][k] - hist[-3][k]) <= 1e-3 * hist[-1][k] for k in (0, 1)):
+                break
+            chunk = min(2 * chunk, 16_000)
+        fin = r.diagnostics()
+    return g, B0, x, B, J, fin, done
+
+
+@pytest.fixture(scope="module")
+def runs():
+    out = {}
+    for n in SIZES:
+        banner(f"IsoHelix phi = pi/4, {n}^3, FP64")
+        out[n] = relax(n)
+    return out
+
+
+def test_isohelix_relaxed_state_matches_table1(runs):
+    paper = table1()
+    table = {}
+    for n, (g, B0, x, B, J, fin, steps) in runs.items():
+        sB, sx, eps = relaxed_state_errors(g, x, B, J)
+        table[n] = (fin["xi"], eps, sB, sx)
+        o = oracle.fields(g, x, B0)
+        assert nrel(B, o["B"]) < 1e-12 and nrel(J, o["J"]) < 1e-11
+        p = paper[n]
+        banner(f"n {n}: xi {fin['xi']:.2e} eps* {eps:.2e} sigma_B {sB:.2e} sigma_x {sx:.2e} ({steps} steps) | "
+               f"Table 1: eps* {p[1]:.1e} sigma_B {p[2]:.1e} sigma_x {p[3]:.1e}")
+        for k in (1, 2, 3):
+            assert 1 / 1.3 < table[n][k] / p[k] < 1.3, (n, k, table[n][k], p[k])
+        assert fin["xi"] < 1e-4
+    ns = sorted(table)
+    for a, b in zip(ns, ns[1:]):
+        assert table[b][2] < 0.5 * table[a][2]  # sigma_B falls with resolution
+        assert table[b][3] <= 1.05 * table[a][3]  # sigma_x does not grow
+        assert table[b][1] < table[a][1]  # eps* falls with resolution

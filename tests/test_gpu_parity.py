@@ -52,16 +52,20 @@ def step_for(g, x0, B0, frac=0.02):
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
-def test_velocity_and_diagnostics(case):
-    banner(f"velocity/diagnostics {case[0]}")
+def test_velocity_fields_and_diagnostics(case):
+    banner(f"velocity/fields/diagnostics {case[0]}")
     g, x0, B0 = make_case(*case)
     tau = oracle.null_threshold(B0)
     with context(g, x0, B0) as r:
         u = host(r.velocity())
         d = r.diagnostics()
+        Bt, Jt = r.fields()
+        B, J = host(Bt), host(Jt)
     o = oracle.fields(g, x0, B0)
     od = oracle.diagnostics(g, x0, B0, tau)
     assert nrel(u, o["u"]) < 1e-12
+    assert nrel(B, o["B"]) < 1e-13
+    assert nrel(J, o["J"]) < 1e-12
     assert rel(d["E_M"], od["E_M"]) < 1e-12
     assert rel(d["R2"], od["R2"]) < 1e-11
     assert rel(d["xi"], od["xi"]) < 1e-11
@@ -126,6 +130,24 @@ def test_single_twist_100_adaptive_steps():
     E = np.array([d["E_M"] for d in diag])
     assert np.abs(E - ref["diag"][:, 2]).max() / E[0] < 1e-11
     assert np.all(E[1:] <= E[:-1] * (1 + 1e-14))
+
+
+def test_single_twist_adaptive_with_safety_factor():
+    """The step-size rule with a safety factor 0.9 on the device vs on the host."""
+    banner("single twist 16^3: 60 adaptive steps, safety 0.9")
+    w = W.single_twist_16()
+    with context(w.grid, w.x0, w.B0, dt0=w.dt0, tol=w.tol, safety=0.9) as r:
+        diag = r.step(60)
+        xK = host(r.state()[0])
+    o = oracle.run(w.grid, w.x0, w.B0, 60, dt=w.dt0, tol=w.tol, safety=0.9)
+    gdt = np.array([d["dt"] for d in diag])
+    od = o["diag"]
+    knife = np.abs(od[:, 5] / w.tol - 1) < 1e-6
+    if not knife.any():
+        assert [d["rejects"] for d in diag] == list(od[:, 7].astype(int))
+        assert np.allclose(gdt, od[:, 1], rtol=1e-6, atol=0)
+    ref = oracle.run(w.grid, w.x0, w.B0, 60, dt=gdt[0], mode=oracle.MODE_REPLAY, dts=gdt)
+    assert nrel(xK - w.x0, ref["x"] - w.x0) < 1e-9
 
 
 def test_deterministic_and_tiling_invariant(monkeypatch):

@@ -290,6 +290,26 @@ def test_T10_controller_rule_table():
     assert acc and d == pytest.approx(dt * 10 ** 0.2, rel=1e-15)
     acc, d = oracle.controller(dt, 0.0, tol)  # zero error: grow 5x
     assert acc and d == 5 * dt
+    # a safety factor scales the new step of the rule (reject and grow), not a kept step
+    acc, d = oracle.controller(dt, 3 * tol, tol, safety=0.9)
+    assert not acc and d == pytest.approx(0.9 * dt * (1 / 3) ** 0.2, rel=1e-15)
+    acc, d = oracle.controller(dt, 0.1 * tol, tol, safety=0.9)
+    assert acc and d == pytest.approx(0.9 * dt * 10 ** 0.2, rel=1e-15)
+    acc, d = oracle.controller(dt, 0.7 * tol, tol, safety=0.9)
+    assert acc and d == dt
+
+
+def test_T10_safety_ends_reject_runs():
+    """Near equilibrium the explicit step is stability-limited and Lambda barely depends on
+    dt; with the rule as printed (safety 1) each retry then shrinks dt by (Lambda0/Lambda)^0.2
+    ~ 1.  With safety 0.9 a rejected attempt's retry is at most 0.9 dt, so the number of
+    rejects per accepted step stays small (IsoHelix, 17^3, steps 1000-1400)."""
+    n = 17
+    g = W.make_grid((n, n, n), [(-4, 4), (-4, 4), (-10, 10)], (0, 0, 0))
+    B0 = W.isohelix_field(g, math.pi / 4)
+    r = oracle.run(g, g.identity(), B0, 1400, dt=1e-3, tol=1e-8, safety=0.9)
+    rej = r["diag"][1000:, 7]
+    assert r["status"] == 0 and rej.max() <= 3 and rej.mean() < 1.5
 
 
 def test_T10_run_matches_rule_applied_by_hand():
@@ -308,6 +328,22 @@ def test_T10_run_matches_rule_applied_by_hand():
         assert r["diag"][s, 1] == dt and r["diag"][s, 7] == rejects and r["diag"][s, 5] == lam
         x, dt = xn, dn
     assert np.array_equal(x, r["x"]) and r["dt"] == dt
+
+
+# --------------------------------------------------------------------------------------
+# T13: the relaxed IsoHelix field against the paper's Table 1 (mimetic, phi = pi/4, 17^3)
+# --------------------------------------------------------------------------------------
+def test_T13_isohelix_17_relaxed_state_matches_table1():
+    """The oracle relaxes the IsoHelix field on the 17^3 grid of Table 1 (Lambda0 = 1e-8,
+    safety 0.9) to the asymptotic sigma_B, sigma_x and eps* the paper prints, within 10 %."""
+    from isohelix_util import PHI, grid, relaxed_state_errors, table1
+    g = grid(17)
+    B0 = W.isohelix_field(g, PHI)
+    r = oracle.run(g, g.identity(), B0, 4000, dt=1e-3, tol=1e-8, safety=0.9)
+    f = oracle.fields(g, r["x"], B0)
+    sB, sx, eps = relaxed_state_errors(g, r["x"], f["B"], f["J"])
+    p = table1()[17]
+    assert abs(eps / p[1] - 1) < 0.1 and abs(sB / p[2] - 1) < 0.1 and abs(sx / p[3] - 1) < 0.1, (eps, sB, sx)
 
 
 # --------------------------------------------------------------------------------------
