@@ -90,7 +90,9 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
     achieved = kernels[dom]["GB/s"]
     tag = "fp64" if precision == R.RELAX_FP64 else "fp32-mixed"
     traffic = measured_traffic(int(dom[-1]), tag, w.name.replace("^3", ""))
-    step_bytes = sum(bytes_node) * N
+    # bytes per accepted step, rejected attempts included: each stage's bytes times its
+    # launches per accepted step in the profiled pass (stage 1 runs once per accepted step)
+    step_bytes = sum(bytes_node[s - 1] * (prof[f"stage{s}"][1] if s > 1 else steps) for s in range(1, 7)) / steps * N
     out.update(
         value=N * steps / wall,
         ms_per_step=wall * 1e3 / steps,

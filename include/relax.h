@@ -82,6 +82,10 @@ typedef struct {
   double Lambda;  /* error estimate max |x5 - x4| of the accepted attempt */
   double min_det; /* min det F over all nodes */
   int rejects;    /* rejected attempts before acceptance */
+  int concave;    /* nodes that are not convex (Sec. 3.2.3, eq. "convexity": some trihedron of
+                     edge vectors to neighbours has the wrong determinant sign; trihedra beyond
+                     a line-tied face are not formed).  Evaluated by relax_diagnostics only;
+                     0 in the per-step records of relax_step. */
 } relax_diag;
 
 /* Bytes of device workspace a context with this configuration needs.  K_record is the
@@ -104,7 +108,7 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
 int relax_step(void* ctx, int K, relax_diag* host_diag, int* steps_done);
 
 /* FP64 diagnostics sweep of the current positions (also for a mixed-precision context):
- * fills t, dt (next step size), E_M, xi, R2, min_det; Lambda and rejects are 0. */
+ * fills t, dt (next step size), E_M, xi, R2, min_det and concave; Lambda and rejects are 0. */
 int relax_diagnostics(void* ctx, relax_diag* out);
 
 /* Velocity u = gamma J x B of the current positions (Sec. 1, eq. "magneto friction", with

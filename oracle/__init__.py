@@ -38,6 +38,8 @@ def lib():
     L.orc_fields.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_diagnostics.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, _dp]
     L.orc_ck_attempt.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_double, _dp, d3, C.c_void_p]
+    L.orc_convexity.argtypes = [i3, d3, i3, _dp, C.c_void_p, C.POINTER(C.c_long)]
+    L.orc_convexity.restype = C.c_int
     L.orc_controller.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, d3]
     L.orc_run.argtypes = [i3, d3, i3, C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_double,
                           C.c_int, _dp, _dp, d3, d3, C.c_void_p, C.c_void_p, C.POINTER(C.c_int)]
@@ -66,6 +68,15 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _vec(grid, a, name="field"):
+    """a as a contiguous FP64 [3][nz][ny][nx] array of this grid (shape checked)."""
+    a = _f64(a)
+    want = (3, int(grid.n[2]), int(grid.n[1]), int(grid.n[0]))
+    if a.shape != want:
+        raise ValueError(f"{name} has shape {a.shape}, expected {want}")
+    return a
+
+
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
@@ -83,12 +94,21 @@ def _check(rc):
 
 def fields(grid, x, B0, gamma=1.0):
     """B, Delta, J, u at every node of positions x (J and u are zero on line-tied faces)."""
-    x, B0 = _f64(x), _f64(B0)
+    x, B0 = _vec(grid, x, "x"), _vec(grid, B0, "B0")
     shp = x.shape
     B, J, u = np.empty(shp), np.empty(shp), np.empty(shp)
     det = np.empty(shp[1:])
     _check(lib().orc_fields(*_g(grid), gamma, x, B0, _ptr(B), _ptr(det), _ptr(J), _ptr(u)))
     return {"B": B, "det": det, "J": J, "u": u}
+
+
+def convexity(grid, x):
+    """(kappa (nz, ny, nx) int array of +1 / -1, number of concave nodes) of positions x."""
+    x = _vec(grid, x, "x")
+    kappa = np.empty(x.shape[1:], dtype=np.int32)
+    count = C.c_long(0)
+    _check(lib().orc_convexity(*_g(grid), x, kappa.ctypes.data_as(C.c_void_p), C.byref(count)))
+    return kappa, int(count.value)
 
 
 def rhs_sampled(grid, x, B0, nodes, gamma=1.0):
@@ -102,7 +122,7 @@ def rhs_sampled(grid, x, B0, nodes, gamma=1.0):
 def diagnostics(grid, x, B0, tau_B2=0.0):
     """{E_M, xi, min_det, R2, skipped} of positions x."""
     out = np.zeros(5)
-    _check(lib().orc_diagnostics(*_g(grid), float(tau_B2), _f64(x), _f64(B0), out))
+    _check(lib().orc_diagnostics(*_g(grid), float(tau_B2), _vec(grid, x, "x"), _vec(grid, B0, "B0"), out))
     return {"E_M": out[0], "xi": out[1], "min_det": out[2], "R2": out[3], "skipped": int(out[4])}
 
 
@@ -144,8 +164,8 @@ def run(grid, x0, B0, K, dt, mode=MODE_ADAPTIVE, tol=1e-7, dt_min=1e-12, t=0.0, 
 
     diag columns: t, dt used, E_M, xi, R2, Lambda, min Delta, rejects (pre-step state).
     """
-    x = _f64(x0).copy()
-    B0 = _f64(B0)
+    x = _vec(grid, x0, "x0").copy()
+    B0 = _vec(grid, B0, "B0")
     tt, dd = C.c_double(t), C.c_double(dt)
     diag = np.zeros((max(K, 1), 8))
     done = C.c_int(0)

@@ -39,7 +39,10 @@
  *   R6 zeta weights apply on line-tied faces only.
  *   R7 xi skips nodes with |B|^2 <= tau_B2 (caller-given absolute threshold).
  *   R8 R2 = 1/2 sum_interior Delta |J x B|^2 dV, the smooth residual.
- *   R9 no safety factor; when Lambda == 0 the step grows by 5x.
+ *   R9 the step-size rule as printed, with an optional safety factor (1 = as printed) on
+ *      the new step; when Lambda == 0 the step grows by 5x.
+ *   R16 convexity: a node is concave when any of its trihedra fails the sign test; trihedra
+ *      reaching beyond a line-tied face are not formed.
  */
 #include <math.h>
 #include <omp.h>
@@ -461,6 +464,54 @@ int orc_rhs_sampled(const int n[3], const double h[3], const int bc[3], double g
   }
   return ORC_OK;
 }
+
+/* Convexity (Sec. 3.2.3, eqs. "dx for convexity", "convexity").  At node p, for each sign
+ * triple (di, dj, dk) in {-1, 1}^3 the trihedron of the edge vectors from x(p) to the
+ * neighbours p + di e_x, p + dj e_y, p + dk e_z; the node is convex (kappa = 1) when every
+ * trihedron's determinant has the sign di dj dk, otherwise concave (kappa = -1).  Trihedra
+ * that would need a neighbour beyond a line-tied face are not formed (reading R16).
+ * kappa: N ints (may be NULL); *concave receives the number of concave nodes. */
+#ifndef ORACLE_COMPLEX
+int orc_convexity(const int n[3], const double h[3], const int bc[3], const double *x, int *kappa,
+                  long *concave) {
+  grid_t g;
+  int rc = grid_init(&g, n, h, bc);
+  if (rc) return rc;
+  long count = 0;
+#pragma omp parallel for reduction(+ : count) schedule(static)
+  for (long m = 0; m < g.N; m++) {
+    const int p[3] = {(int)(m % g.n[0]), (int)((m / g.n[0]) % g.n[1]), (int)(m / ((long)g.n[0] * g.n[1]))};
+    const int zero[3] = {0, 0, 0};
+    double xc[3];
+    position(&g, x, p, zero, xc);
+    int convex = 1;
+    for (int di = -1; di <= 1; di += 2)
+      for (int dj = -1; dj <= 1; dj += 2)
+        for (int dk = -1; dk <= 1; dk += 2) {
+          const int d[3][3] = {{di, 0, 0}, {0, dj, 0}, {0, 0, dk}};
+          double e[3][3];
+          int ok = 1;
+          for (int v = 0; v < 3; v++) {
+            double s3[3];
+            if (neighbour(&g, p, d[v], s3) < 0) { ok = 0; break; }
+            double xn[3];
+            position(&g, x, p, d[v], xn);
+            for (int c = 0; c < 3; c++) e[v][c] = xn[c] - xc[c];
+          }
+          if (!ok) continue;
+          const double det = e[0][0] * (e[1][1] * e[2][2] - e[1][2] * e[2][1]) -
+                             e[0][1] * (e[1][0] * e[2][2] - e[1][2] * e[2][0]) +
+                             e[0][2] * (e[1][0] * e[2][1] - e[1][1] * e[2][0]);
+          const double sgn = (det > 0.0) ? 1.0 : (det < 0.0 ? -1.0 : 0.0);
+          if (sgn != (double)(di * dj * dk)) convex = 0;
+        }
+    if (kappa) kappa[m] = convex ? 1 : -1;
+    count += convex ? 0 : 1;
+  }
+  *concave = count;
+  return ORC_OK;
+}
+#endif
 
 /* Diagnostics of positions x: out = {E_M, xi, min Delta, R2, skipped}. */
 int orc_diagnostics(const int n[3], const double h[3], const int bc[3], double tau_B2, const double *x,

@@ -52,7 +52,8 @@ class relax_config(C.Structure):
 
 class relax_diag(C.Structure):
     _fields_ = [("t", C.c_double), ("dt", C.c_double), ("E_M", C.c_double), ("xi", C.c_double),
-                ("R2", C.c_double), ("Lambda", C.c_double), ("min_det", C.c_double), ("rejects", C.c_int)]
+                ("R2", C.c_double), ("Lambda", C.c_double), ("min_det", C.c_double), ("rejects", C.c_int),
+                ("concave", C.c_int)]
 
 
 _lib = None
@@ -169,7 +170,7 @@ def relax_destroy(ctx) -> None:
 
 # ---- high level --------------------------------------------------------------------------------
 
-DIAG_FIELDS = ("t", "dt", "E_M", "xi", "R2", "Lambda", "min_det", "rejects")
+DIAG_FIELDS = ("t", "dt", "E_M", "xi", "R2", "Lambda", "min_det", "rejects", "concave")
 
 
 def make_config(grid, precision=RELAX_FP64, gamma=1.0, dt0=1e-3, dt_min=1e-12, tol=1e-7, adaptive=True,

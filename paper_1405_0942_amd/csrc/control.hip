@@ -129,8 +129,8 @@ __global__ __launch_bounds__(CT) void control_kernel(Control* ctl, const double*
 __global__ __launch_bounds__(CT) void diag_finish_kernel(const double* __restrict__ part, int nblocks, double dV,
                                                           double* __restrict__ out) {
   const int tid = threadIdx.x;
-  __shared__ double sE[CT], sR[CT], sX[CT], sM[CT], sZ[CT];
-  double E = 0, R = 0, X = 0, M = INFINITY, Z = 0;
+  __shared__ double sE[CT], sR[CT], sX[CT], sM[CT], sZ[CT], sC[CT];
+  double E = 0, R = 0, X = 0, M = INFINITY, Z = 0, Cc = 0;
   for (int b = tid; b < nblocks; b += CT) {
     const double* p = part + (long long)b * NPART;
     E += p[0];
@@ -138,12 +138,14 @@ __global__ __launch_bounds__(CT) void diag_finish_kernel(const double* __restric
     X = max_nan(X, p[2]);
     M = min_nan(M, p[3]);
     Z += p[4];
+    Cc += p[5];
   }
   sE[tid] = E;
   sR[tid] = R;
   sX[tid] = X;
   sM[tid] = M;
   sZ[tid] = Z;
+  sC[tid] = Cc;
   __syncthreads();
   for (int s = CT / 2; s > 0; s >>= 1) {
     if (tid < s) {
@@ -152,6 +154,7 @@ __global__ __launch_bounds__(CT) void diag_finish_kernel(const double* __restric
       sX[tid] = max_nan(sX[tid], sX[tid + s]);
       sM[tid] = min_nan(sM[tid], sM[tid + s]);
       sZ[tid] += sZ[tid + s];
+      sC[tid] += sC[tid + s];
     }
     __syncthreads();
   }
@@ -161,6 +164,7 @@ __global__ __launch_bounds__(CT) void diag_finish_kernel(const double* __restric
     out[2] = sX[0];
     out[3] = sM[0];
     out[4] = sZ[0];
+    out[5] = sC[0];
   }
 }
 
@@ -227,8 +231,8 @@ hipError_t launch_control(Control* ctl, const double* part, const double* lam_pa
   return hipGetLastError();
 }
 
-hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out5, hipStream_t st) {
-  hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(CT), 0, st, part, nblocks, dV, out5);
+hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out6, hipStream_t st) {
+  hipLaunchKernelGGL(diag_finish_kernel, dim3(1), dim3(CT), 0, st, part, nblocks, dV, out6);
   return hipGetLastError();
 }
 

@@ -228,9 +228,9 @@ SweepArgs sweep_args(Ctx* c) {
   return a;
 }
 
-// FP64 diagnostics sweep of x[buf] into d_out[0..4] = {E, R2, xi, min det, nulls}; host copy.
+// FP64 diagnostics sweep of x[buf] into d_out[0..5] = {E, R2, xi, min det, nulls, concave}; host copy.
 // Non-null u_out, B_out, J_out also receive u, B and J of x[buf].
-int diagnostics_sweep(Ctx* c, int buf, double out[5], double* u_out = nullptr, double u_det_scale = 0.0,
+int diagnostics_sweep(Ctx* c, int buf, double out[6], double* u_out = nullptr, double u_det_scale = 0.0,
                       double* B_out = nullptr, double* J_out = nullptr) {
   SweepArgs a = sweep_args(c);
   a.B0 = c->d_B0_64;
@@ -241,9 +241,9 @@ int diagnostics_sweep(Ctx* c, int buf, double out[5], double* u_out = nullptr, d
   a.J_out = J_out;
   HIP_TRY(c, launch_diagnostics(a, c->stream));
   HIP_TRY(c, launch_diag_finish(c->d_part, c->g.nblocks, c->g.dV, c->d_out, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(c->h_ring, c->d_out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_ring, c->d_out, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memcpy(out, c->h_ring, 5 * sizeof(double));
+  std::memcpy(out, c->h_ring, 6 * sizeof(double));
   return RELAX_OK;
 }
 
@@ -401,7 +401,7 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   k.record_cap = c->K_record;
   k.steps_total = 0;
   if ((rc = push_ctl(c)) != RELAX_OK) return bail(rc);
-  double d[5];
+  double d[6];
   if ((rc = diagnostics_sweep(c, 0, d)) != RELAX_OK) return bail(rc);
   if (d[3] != d[3] || !std::isfinite(d[0])) return bail(RELAX_E_NAN);
   if (!(d[3] > 0.0)) return bail(RELAX_E_FOLD);
@@ -442,6 +442,7 @@ int relax_step(void* ctx, int K, relax_diag* host_diag, int* steps_done) {
         o.Lambda = e[5];
         o.min_det = e[6];
         o.rejects = (int)e[7];
+        o.concave = 0;
       }
     }
     done += acc;
@@ -463,7 +464,7 @@ int relax_diagnostics(void* ctx, relax_diag* out) {
   if (c->status != RELAX_OK) return RELAX_E_STATE;
   int rc = sync_ctl(c);
   if (rc) return rc;
-  double d[5];
+  double d[6];
   if ((rc = diagnostics_sweep(c, c->cur, d)) != RELAX_OK) return rc;
   out->t = c->h_ctl->t;
   out->dt = c->h_ctl->dt;
@@ -473,6 +474,7 @@ int relax_diagnostics(void* ctx, relax_diag* out) {
   out->min_det = d[3];
   out->Lambda = 0.0;
   out->rejects = 0;
+  out->concave = (int)d[5];
   return RELAX_OK;
 }
 
@@ -482,7 +484,7 @@ int relax_velocity(void* ctx, double* d_u_out) {
   if (c->status != RELAX_OK) return RELAX_E_STATE;
   int rc = sync_ctl(c);
   if (rc) return rc;
-  double d[5];
+  double d[6];
   return diagnostics_sweep(c, c->cur, d, d_u_out);
 }
 
@@ -492,7 +494,7 @@ int relax_fields(void* ctx, double* d_B_out, double* d_J_out) {
   if (c->status != RELAX_OK) return RELAX_E_STATE;
   int rc = sync_ctl(c);
   if (rc) return rc;
-  double d[5];
+  double d[6];
   return diagnostics_sweep(c, c->cur, d, nullptr, 0.0, d_B_out, d_J_out);
 }
 
@@ -529,7 +531,7 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
   // seed: cotangents of E_M(x_K) and R2(x_K)
   a.useed = nullptr;
   if (seed_R2 != 0.0) {
-    double d[5];
+    double d[6];
     const double gm = c->cfg.gamma;
     if ((rc = diagnostics_sweep(c, c->cur, d, c->d_useed, c->g.dV * seed_R2 / (gm * gm))) != RELAX_OK) return rc;
     a.useed = c->d_useed;
@@ -624,7 +626,7 @@ int relax_set_state(void* ctx, const double* d_x_in, double t, double dt) {
   k.steps_total = 0;
   if ((rc = push_ctl(c)) != RELAX_OK) return rc;
   c->cur = 0;
-  double d[5];
+  double d[6];
   if ((rc = diagnostics_sweep(c, 0, d)) != RELAX_OK) return rc;
   if (d[3] != d[3] || !std::isfinite(d[0])) return fail(c, RELAX_E_NAN, "relax_set_state: non-finite state");
   if (!(d[3] > 0.0)) return fail(c, RELAX_E_FOLD, "relax_set_state: folded grid (min det F <= 0)");

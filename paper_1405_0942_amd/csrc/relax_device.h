@@ -124,7 +124,8 @@ hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st);
 hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st);  // FP64 sweep of x[diag_buf]
 hipError_t launch_control(Control* ctl, const double* part, const double* lam_part, int nblocks,
                           double* ring, double* dt_record, hipStream_t st);
-hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out5, hipStream_t st);
+// out6 = {E_M, R2, xi, min det F, null-guard skips, concave nodes} of a diagnostics sweep
+hipError_t launch_diag_finish(const double* part, int nblocks, double dV, double* out6, hipStream_t st);
 hipError_t launch_begin_chunk(Control* ctl, int target, hipStream_t st);
 hipError_t launch_to_float(const double* src, float* dst, long long n, hipStream_t st);
 hipError_t launch_prescale(double* B0, long long N, const double scale[3], hipStream_t st);

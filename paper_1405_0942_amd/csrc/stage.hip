@@ -444,6 +444,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
 
   // reductions
   double acc_E = 0.0, acc_R2 = 0.0, acc_xi = 0.0, acc_min = INFINITY, acc_null = 0.0, acc_lam = 0.0;
+  double acc_conc = 0.0;  // DIAG: concave nodes
 
   // ---- stores of one output plane (every lane issues them; masked-off lanes are dropped) ----
   // stage 1: k_1 (or u, in a diagnostics sweep that asks for it) and the checkpoint copy of
@@ -577,6 +578,40 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                   Bd[m] = (F[m][0] * (double)q0 + F[m][1] * (double)q1 + F[m][2] * (double)q2) * rD;
                 acc_E += zeta * (Bd[0] * Bd[0] + Bd[1] * Bd[1] + Bd[2] * Bd[2]) * Dp;
                 acc_min = (Dp < acc_min || Dp != Dp) ? Dp : acc_min;
+                if constexpr (DIAG) {
+                  // convexity (Sec. 3.2.3, eq. "convexity"): every trihedron of edge vectors to
+                  // the neighbours p + di e_x, p + dj e_y, p + dk e_z must have a determinant of
+                  // sign di dj dk; trihedra beyond a line-tied face are not formed
+                  const int oc = (r1 + 1) * RX2 + (c1 + 1), sc = mod3(p);
+                  const bool lox = XYP || bcx == BC_PERIODIC || gi > 0, hix = XYP || bcx == BC_PERIODIC || gi < nx - 1;
+                  const bool loy = XYP || bcy == BC_PERIODIC || gj > 0, hiy = XYP || bcy == BC_PERIODIC || gj < ny - 1;
+                  const bool loz = bcz == BC_PERIODIC || p > 0, hiz = bcz == BC_PERIODIC || p < nz - 1;
+                  double ex[2][3], ey[2][3], ez[2][3];  // [0]: toward -, [1]: toward +
+#pragma unroll
+                  for (int m = 0; m < 3; m++) {
+                    const double c0 = ys[sc][m][oc];
+                    ex[0][m] = ys[sc][m][oc - 1] - c0;
+                    ex[1][m] = ys[sc][m][oc + 1] - c0;
+                    ey[0][m] = ys[sc][m][oc - RX2] - c0;
+                    ey[1][m] = ys[sc][m][oc + RX2] - c0;
+                    ez[0][m] = loz ? ys[mod3(p - 1)][m][oc] - c0 : 0.0;
+                    ez[1][m] = hiz ? ys[mod3(p + 1)][m][oc] - c0 : 0.0;
+                  }
+                  bool convex = true;
+#pragma unroll
+                  for (int t = 0; t < 8; t++) {
+                    const int a = t & 1, b = (t >> 1) & 1, c = (t >> 2) & 1;
+                    const bool formed = (a ? hix : lox) && (b ? hiy : loy) && (c ? hiz : loz);
+                    const double* u1 = ex[a];
+                    const double* u2 = ey[b];
+                    const double* u3 = ez[c];
+                    const double det = u1[0] * (u2[1] * u3[2] - u2[2] * u3[1]) - u1[1] * (u2[0] * u3[2] - u2[2] * u3[0]) +
+                                       u1[2] * (u2[0] * u3[1] - u2[1] * u3[0]);
+                    const double want = ((a + b + c) & 1) ? 1.0 : -1.0;  // (2a-1)(2b-1)(2c-1)
+                    if (formed && !(det * want > 0.0)) convex = false;
+                  }
+                  acc_conc += convex ? 0.0 : 1.0;
+                }
               }
             }
           }
@@ -748,23 +783,25 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   const int wave = tid >> 6, lane = tid & 63;
   if (STAGE1) {
     const double e = wave_sum(acc_E), r2 = wave_sum(acc_R2), xi = wave_max(acc_xi), mn = wave_min(acc_min),
-                 nl = wave_sum(acc_null);
+                 nl = wave_sum(acc_null), cc = wave_sum(acc_conc);
     if (lane == 0) {
       red[wave][0] = e;
       red[wave][1] = r2;
       red[wave][2] = xi;
       red[wave][3] = mn;
       red[wave][4] = nl;
+      red[wave][5] = cc;
     }
     __syncthreads();
     if (tid == 0) {
-      double E = 0, R = 0, X = 0, M = INFINITY, Z = 0;
+      double E = 0, R = 0, X = 0, M = INFINITY, Z = 0, Cc = 0;
       for (int w = 0; w < NTHREADS / 64; w++) {
         E += red[w][0];
         R += red[w][1];
         X = (red[w][2] > X || red[w][2] != red[w][2]) ? red[w][2] : X;
         M = (red[w][3] < M || red[w][3] != red[w][3]) ? red[w][3] : M;
         Z += red[w][4];
+        Cc += red[w][5];
       }
       double* pp = a.part + (long long)blockIdx.x * NPART;
       pp[0] = E;
@@ -772,6 +809,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       pp[2] = X;
       pp[3] = M;
       pp[4] = Z;
+      pp[5] = Cc;
     }
   }
   if (LAST) {

@@ -1,0 +1,71 @@
+"""Breakdown of the mimetic relaxation on concave grids (Sec. 4.4, the Pontin09 field with
+phi_{1,2} = +-pi), watched with the convexity monitor (Sec. 3.2.3, eq. "convexity").
+
+The paper reports that for this strongly twisted field the relaxing grid develops concave
+cells, then jagged distortions, and the mimetic run breaks down (the diagnostics blow up and
+the step size drops by orders of magnitude); a finer grid delays the blow-up.  Here, on the
+33^3 grid over [-4, 4]^2 x [-10, 10] (all faces line-tied, twist regions at Z = -5 and +5,
+Lambda0 = 1e-7, safety 0.9, dt_min = 1e-9):
+  * concave nodes appear long before the end, and their number keeps growing;
+  * xi first falls (relaxation), then grows again while E_M, which magneto-friction can only
+    lower, turns upward;
+  * the run ends with the step size below dt_min (RELAX_E_DT).
+RELAX_BREAKDOWN_FULL=1 also runs 65^3 and checks that the breakdown comes later there.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import paper_1405_0942_amd as R
+import workloads as W
+from gpu_util import banner, context
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def run_to_breakdown(n, max_steps):
+    g = W.make_grid((n, n, n), [(-4.0, 4.0), (-4.0, 4.0), (-10.0, 10.0)], (0, 0, 0))
+    B0 = W.pontin09_field(g)
+    rows = []
+    with context(g, g.identity(), B0, dt0=1e-3, tol=1e-7, safety=0.9, dt_min=1e-9) as r:
+        done, status = 0, 0
+        while done < max_steps:
+            d = r.step(500, raise_on_error=False)
+            done += len(d)
+            status = r.last_status
+            if status != R.RELAX_OK:
+                break
+            dd = r.diagnostics()
+            rows.append((d[-1]["t"], dd["concave"], dd["xi"], dd["E_M"], dd["min_det"]))
+            banner(f"  n {n}: step {done} t {rows[-1][0]:.2f} concave {rows[-1][1]} xi {rows[-1][2]:.2e} "
+                   f"E_M {rows[-1][3]:.6f} min det {rows[-1][4]:.3e}")
+        t_end = r.state()[1]
+    return np.array(rows), status, t_end
+
+
+def test_pontin09_concavity_precedes_breakdown():
+    banner("Pontin09 phi = +-pi, 33^3: relax until the mimetic run breaks down")
+    rows, status, t_end = run_to_breakdown(33, 20_000)
+    assert status == R.RELAX_E_DT
+    t, concave, xi, E = rows[:, 0], rows[:, 1], rows[:, 2], rows[:, 3]
+    first = int(np.argmax(concave > 0))
+    assert concave[first] > 0 and t[first] < 0.5 * t_end  # concave cells long before the end
+    assert concave[-1] > 2 * concave[first]  # and spreading
+    i_min = int(np.argmin(xi))
+    assert xi[i_min] < 0.02 and xi[-1] > 3 * xi[i_min]  # relaxation, then growing force
+    j_min = int(np.argmin(E))
+    assert j_min < len(E) - 1 and E[-1] > E[j_min] * (1 + 1e-5)  # the energy turns upward
+    banner(f"  first concave at t {t[first]:.1f}, min xi {xi[i_min]:.2e} at t {t[i_min]:.1f}, "
+           f"E_M minimum at t {t[j_min]:.1f}, breakdown at t {t_end:.2f}")
+
+
+@pytest.mark.skipif(os.environ.get("RELAX_BREAKDOWN_FULL") != "1", reason="65^3 run: RELAX_BREAKDOWN_FULL=1")
+def test_pontin09_breakdown_later_on_finer_grid():
+    _, s33, t33 = run_to_breakdown(33, 20_000)
+    _, s65, t65 = run_to_breakdown(65, 200_000)
+    assert s33 == s65 == R.RELAX_E_DT and t65 > 1.5 * t33

@@ -66,10 +66,29 @@ def test_velocity_fields_and_diagnostics(case):
     assert nrel(u, o["u"]) < 1e-12
     assert nrel(B, o["B"]) < 1e-13
     assert nrel(J, o["J"]) < 1e-12
+    assert d["concave"] == oracle.convexity(g, x0)[1]
     assert rel(d["E_M"], od["E_M"]) < 1e-12
     assert rel(d["R2"], od["R2"]) < 1e-11
     assert rel(d["xi"], od["xi"]) < 1e-11
     assert rel(d["min_det"], od["min_det"]) < 1e-13
+
+
+CONCAVE_CASES = [((20, 18, 16), (0, 0, 0), 0.7, 3.0), ((24, 16, 12), (1, 1, 1), 0.7, 3.0),
+                 ((70, 11, 37), (1, 1, 0), 0.8, 4.0), ((66, 13, 40), (1, 1, 1), 0.65, 5.0)]
+
+
+@pytest.mark.parametrize("case", CONCAVE_CASES, ids=[f"{c[0]}-{c[1]}" for c in CONCAVE_CASES])
+def test_concave_count_matches_oracle(case):
+    """Grids with a few dozen concave nodes (a checkerboard bump) and det F near 1."""
+    n, bc, amp, width = case
+    banner(f"convexity {n} {bc}")
+    g = W.make_grid(n, [(-1.0, 1.3), (-0.4, 0.6), (-2.0, 2.0)], bc)
+    x0 = W.distorted_grid(g, 0.05 * min(g.h), seed=5) + W.checkerboard_bump(g, amp, width)
+    B0 = W.smooth_random_field(g, 0.6, seed=200) + np.array([0.2, -0.1, 1.0])[:, None, None, None]
+    with context(g, x0, B0) as r:
+        d = r.diagnostics()
+    count = oracle.convexity(g, x0)[1]
+    assert count > 0 and d["concave"] == count
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])

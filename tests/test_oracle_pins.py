@@ -347,6 +347,47 @@ def test_T13_isohelix_17_relaxed_state_matches_table1():
 
 
 # --------------------------------------------------------------------------------------
+# T14: convexity (Sec. 3.2.3, eqs. "dx for convexity", "convexity")
+# --------------------------------------------------------------------------------------
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0), (1, 1, 1), (0, 1, 0)])
+def test_T14_convexity_undistorted_grid(bc):
+    g = W.make_grid((7, 8, 9), [(-1.0, 1.0), (0.0, 2.0), (-3.0, 3.0)], bc)
+    kappa, count = oracle.convexity(g, g.identity())
+    assert count == 0 and np.all(kappa == 1)
+
+
+def test_T14_convexity_affine_maps():
+    """x = A X + b on a line-tied grid: every trihedron's determinant is det A times that of
+    the undistorted one, so det A > 0 keeps every node convex and det A < 0 makes all concave."""
+    g = W.make_grid((6, 7, 8), [(-1.0, 1.0)] * 3, (0, 0, 0))
+    X = g.identity()
+    A = np.array([[1.2, 0.4, -0.3], [0.1, 0.9, 0.5], [-0.2, 0.3, 1.1]])
+    assert np.linalg.det(A) > 0
+    x = np.einsum("ij,j...->i...", A, X) + np.array([0.3, -0.2, 0.7])[:, None, None, None]
+    assert oracle.convexity(g, x)[1] == 0
+    R = A @ np.diag([1.0, -1.0, 1.0])  # det < 0
+    x = np.einsum("ij,j...->i...", R, X)
+    kappa, count = oracle.convexity(g, x)
+    assert count == g.N and np.all(kappa == -1)
+
+
+def test_T14_convexity_one_folded_node():
+    """Dragging one interior node past its +x neighbour reverses the edges it shares, so that
+    node is concave; only trihedra that contain it change, so at most it and its 6 neighbours
+    become concave."""
+    g = W.make_grid((8, 8, 8), [(0.0, 1.0)] * 3, (0, 0, 0))
+    x = g.identity().copy()
+    i, j, k = 3, 4, 4
+    x[0, k, j, i] = x[0, k, j, i + 1] + 0.5 * g.h[0]
+    kappa, count = oracle.convexity(g, x)
+    assert kappa[k, j, i] == -1 and 1 <= count <= 7
+    bad = set(zip(*np.nonzero(kappa == -1)))
+    near = {(k, j, i)} | {(k + dk, j + dj, i + di) for di, dj, dk in
+                          [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]}
+    assert bad <= near
+
+
+# --------------------------------------------------------------------------------------
 # T11: invariances: translation, cyclic permutation of the axes, periodic roll
 # --------------------------------------------------------------------------------------
 def test_T11_translation():

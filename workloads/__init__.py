@@ -147,6 +147,22 @@ def isohelix_field(g: Grid, phi=math.pi / 4, B0=1.0, ar=math.sqrt(2.0), az=2.0) 
     return np.ascontiguousarray(np.stack([Y * amp, -X * amp, B0 * np.ones_like(X)]))
 
 
+def pontin09_field(g: Grid, phis=(math.pi, -math.pi), Ls=(-5.0, 5.0), B0=1.0, ar=math.sqrt(2.0),
+                   az=2.0) -> np.ndarray:
+    """Pontin09 initial field (Sec. 3.1, eq. "B init Pontin09"): B0 e_z plus two twist regions
+    (2 B0 phi_i / (pi a_r)) e^{-(X^2+Y^2)/a_r^2 - (Z-L_i)^2/a_z^2} (-Y, X, 0) centred at
+    Z = L_i.  The paper does not give L_i; the default puts them half way to the ends of the
+    [-10, 10] box."""
+    X, Y, Z = g.coords()
+    bx = np.zeros_like(X)
+    by = np.zeros_like(X)
+    for phi, L in zip(phis, Ls):
+        amp = (2.0 * B0 * phi / (math.pi * ar)) * np.exp(-(X ** 2 + Y ** 2) / ar ** 2 - (Z - L) ** 2 / az ** 2)
+        bx += -Y * amp
+        by += X * amp
+    return np.ascontiguousarray(np.stack([bx, by, B0 * np.ones_like(X)]))
+
+
 def isohelix_relaxed_map(g: Grid, phi=math.pi / 4, ar=math.sqrt(2.0), az=2.0) -> np.ndarray:
     """Closed-form relaxed positions of the IsoHelix field (Sec. 3.1, eq. "x analytical relaxed")."""
     X, Y, Z = g.coords()
@@ -279,6 +295,20 @@ def abc_box(n: int = 256, seed: int = 5, amp: float = 0.1) -> Workload:
 # ----------------------------------------------------------------------------------------
 # Generic seeded inputs for operator tests
 # ----------------------------------------------------------------------------------------
+
+def checkerboard_bump(g: Grid, amp_rel: float, width: float) -> np.ndarray:
+    """x-displacement (-1)^(i+j+k) amp_rel h_x exp(-|idx - centre|^2 / width^2) (index units).
+
+    Central differences of a checkerboard cancel, so det F stays near 1 while the edges to
+    neighbours flip once amp_rel exceeds 1/2: concave cells inside a smooth grid."""
+    nx, ny, nz = g.n
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    c = np.where((i + j + k) % 2 == 0, 1.0, -1.0)
+    r2 = ((i - nx / 2) ** 2 + (j - ny / 2) ** 2 + (k - nz / 2) ** 2) / width ** 2
+    d = np.zeros(g.shape)
+    d[0] = amp_rel * g.h[0] * c * np.exp(-r2)
+    return d
+
 
 def smooth_random_field(g: Grid, amp: float, seed: int, mmax: int = 2) -> np.ndarray:
     """Sum of random low-order cosine modes, periodic along periodic axes.
