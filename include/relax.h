@@ -124,6 +124,16 @@ int relax_velocity(void* ctx, double* d_u_out);
  * Blocks until done. */
 int relax_fields(void* ctx, double* d_B_out, double* d_J_out);
 
+/* Breakdown monitors of the current positions, per node ([nz][ny][nx], device, overwritten):
+ * d_alpha_out (FP64) receives alpha* = J.B / |B|^2 (Sec. 3.2.1; constant along field lines in a
+ * force-free state; 0 where B = 0 and on line-tied faces, where J is 0), with B and J as
+ * relax_fields gives them; d_kappa_out (int32) receives the convexity of Sec. 3.2.3
+ * (eq. "convexity"): +1 if every trihedron of edge vectors to the neighbours
+ * x(i +- 1, j, k), x(i, j +- 1, k), x(i, j, k +- 1) has the determinant sign of its
+ * orientation, else -1 (trihedra beyond a line-tied face are not formed; the count of -1 nodes
+ * is relax_diag.concave).  Either pointer may be NULL.  Blocks until done. */
+int relax_monitors(void* ctx, double* d_alpha_out, int* d_kappa_out);
+
 /* Reverse-mode gradient through the recorded fixed-dt trajectory (record = 1):
  * d(seed_EM * E_M(x_K) + seed_R2 * R2(x_K)) / d(x0, B0), where x_K is the current state
  * and x0 the state at init / relax_set_state.  d_grad_x0, d_grad_B0: [3][nz][ny][nx] FP64

@@ -102,6 +102,18 @@ def fields(grid, x, B0, gamma=1.0):
     return {"B": B, "det": det, "J": J, "u": u}
 
 
+def alpha_star(grid, x, B0):
+    """alpha* = J.B / |B|^2 at every node (Sec. 3.2.1), with B and J of fields(); 0 where B = 0
+    (and on line-tied faces, where J is zero).  Shape (nz, ny, nx)."""
+    f = fields(grid, x, B0)
+    B, J = f["B"], f["J"]
+    B2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2]
+    JB = J[0] * B[0] + J[1] * B[1] + J[2] * B[2]
+    out = np.zeros_like(B2)
+    np.divide(JB, B2, out=out, where=B2 > 0)
+    return out
+
+
 def convexity(grid, x):
     """(kappa (nz, ny, nx) int array of +1 / -1, number of concave nodes) of positions x."""
     x = _vec(grid, x, "x")

@@ -25,7 +25,7 @@ RELAX_FP64, RELAX_FP32_MIXED = 0, 1
 
 # every symbol include/relax.h declares
 EXPORTS = ("relax_workspace_bytes", "relax_init", "relax_step", "relax_diagnostics", "relax_velocity",
-           "relax_fields", "relax_backward",
+           "relax_fields", "relax_monitors", "relax_backward",
            "relax_get_state", "relax_set_state", "relax_profile", "relax_strerror", "relax_last_error",
            "relax_destroy")
 
@@ -78,6 +78,7 @@ def lib():
     L.relax_diagnostics.argtypes = [vp, C.POINTER(relax_diag)]
     L.relax_velocity.argtypes = [vp, vp]
     L.relax_fields.argtypes = [vp, vp, vp]
+    L.relax_monitors.argtypes = [vp, vp, vp]
     L.relax_backward.argtypes = [vp, C.c_double, C.c_double, vp, vp]
     L.relax_get_state.argtypes = [vp, vp, dp, dp]
     L.relax_set_state.argtypes = [vp, vp, C.c_double, C.c_double]
@@ -89,8 +90,8 @@ def lib():
     L.relax_last_error.restype = C.c_char_p
     L.relax_destroy.argtypes = [vp]
     L.relax_destroy.restype = None
-    for name in ("relax_init", "relax_step", "relax_diagnostics", "relax_velocity", "relax_fields", "relax_backward",
-                 "relax_get_state",
+    for name in ("relax_init", "relax_step", "relax_diagnostics", "relax_velocity", "relax_fields", "relax_monitors",
+                 "relax_backward", "relax_get_state",
                  "relax_set_state"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -129,6 +130,10 @@ def relax_velocity(ctx, d_u_out):
 
 def relax_fields(ctx, d_B_out, d_J_out):
     return lib().relax_fields(ctx, C.c_void_p(d_B_out), C.c_void_p(d_J_out))
+
+
+def relax_monitors(ctx, d_alpha_out, d_kappa_out):
+    return lib().relax_monitors(ctx, C.c_void_p(d_alpha_out), C.c_void_p(d_kappa_out))
 
 
 def relax_backward(ctx, seed_EM, seed_R2, d_grad_x0, d_grad_B0):
@@ -259,6 +264,15 @@ class Relaxation:
         J = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         self._check(relax_fields(self.ctx, B.data_ptr(), J.data_ptr()), "relax_fields")
         return B, J
+
+    def monitors(self):
+        """(alpha*, kappa) of the current positions as new device tensors of shape (nz, ny, nx):
+        alpha* = J.B / B^2 (FP64) and the node convexity +1 / -1 (int32)."""
+        import torch
+        alpha = torch.empty(self.shape[1:], dtype=torch.float64, device=self.device)
+        kappa = torch.empty(self.shape[1:], dtype=torch.int32, device=self.device)
+        self._check(relax_monitors(self.ctx, alpha.data_ptr(), kappa.data_ptr()), "relax_monitors")
+        return alpha, kappa
 
     def state(self):
         """(x as a new device tensor, t, dt)"""

@@ -229,9 +229,11 @@ SweepArgs sweep_args(Ctx* c) {
 }
 
 // FP64 diagnostics sweep of x[buf] into d_out[0..5] = {E, R2, xi, min det, nulls, concave}; host copy.
-// Non-null u_out, B_out, J_out also receive u, B and J of x[buf].
+// Non-null u_out, B_out, J_out, alpha_out, kappa_out also receive u, B, J, alpha* and the
+// convexity of x[buf].
 int diagnostics_sweep(Ctx* c, int buf, double out[6], double* u_out = nullptr, double u_det_scale = 0.0,
-                      double* B_out = nullptr, double* J_out = nullptr) {
+                      double* B_out = nullptr, double* J_out = nullptr, double* alpha_out = nullptr,
+                      int* kappa_out = nullptr) {
   SweepArgs a = sweep_args(c);
   a.B0 = c->d_B0_64;
   a.diag_buf = buf;
@@ -239,6 +241,8 @@ int diagnostics_sweep(Ctx* c, int buf, double out[6], double* u_out = nullptr, d
   a.u_det_scale = u_det_scale;
   a.B_out = B_out;
   a.J_out = J_out;
+  a.alpha_out = alpha_out;
+  a.kappa_out = kappa_out;
   HIP_TRY(c, launch_diagnostics(a, c->stream));
   HIP_TRY(c, launch_diag_finish(c->d_part, c->g.nblocks, c->g.dV, c->d_out, c->stream));
   HIP_TRY(c, hipMemcpyAsync(c->h_ring, c->d_out, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -496,6 +500,16 @@ int relax_fields(void* ctx, double* d_B_out, double* d_J_out) {
   if (rc) return rc;
   double d[6];
   return diagnostics_sweep(c, c->cur, d, nullptr, 0.0, d_B_out, d_J_out);
+}
+
+int relax_monitors(void* ctx, double* d_alpha_out, int* d_kappa_out) {
+  Ctx* c = static_cast<Ctx*>(ctx);
+  if (!c) return RELAX_E_ARG;
+  if (c->status != RELAX_OK) return RELAX_E_STATE;
+  int rc = sync_ctl(c);
+  if (rc) return rc;
+  double d[6];
+  return diagnostics_sweep(c, c->cur, d, nullptr, 0.0, nullptr, nullptr, d_alpha_out, d_kappa_out);
 }
 
 int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0, double* d_grad_B0) {

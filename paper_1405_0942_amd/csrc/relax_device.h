@@ -79,6 +79,8 @@ struct SweepArgs {
   double u_det_scale;  // diagnostics sweep only: if not 0, u_out holds u * det F * u_det_scale
   double* B_out;       // diagnostics sweep only: if not null, receives B(x) [3][N]
   double* J_out;       // diagnostics sweep only: if not null, receives J(x) [3][N] (0 on line-tied faces)
+  double* alpha_out;   // diagnostics sweep only: if not null, receives alpha* = J.B / B^2 [N]
+  int* kappa_out;      // diagnostics sweep only: if not null, receives the convexity +1 / -1 [N]
 };
 
 // Arguments of the reverse-mode sweeps (adjoint.hip).  FP64 throughout.

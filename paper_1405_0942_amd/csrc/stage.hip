@@ -445,6 +445,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   // reductions
   double acc_E = 0.0, acc_R2 = 0.0, acc_xi = 0.0, acc_min = INFINITY, acc_null = 0.0, acc_lam = 0.0;
   double acc_conc = 0.0;  // DIAG: concave nodes
+  int kap_q = 1;          // DIAG: convexity of the own node of the output plane q
 
   // ---- stores of one output plane (every lane issues them; masked-off lanes are dropped) ----
   // stage 1: k_1 (or u, in a diagnostics sweep that asks for it) and the checkpoint copy of
@@ -477,12 +478,17 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       double* dJ = a.J_out ? a.J_out : fb;
       const unsigned eu = (on && a.u_out) ? out_e : IE, eB = (on && a.B_out) ? out_e : IE;
       const unsigned eJ = (on && a.J_out) ? out_e : IE;
+      double* dA = a.alpha_out ? a.alpha_out : fb;
+      int* dK = a.kappa_out ? a.kappa_out : reinterpret_cast<int*>(fb);
+      const unsigned eA = (on && a.alpha_out) ? out_e : IE, eK = (on && a.kappa_out) ? out_e : IE;
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(du + m * N + zo, nxy), eu, (double)so_k[m]);
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dB + m * N + zo, nxy), eB, so_p[0][m]);
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dJ + m * N + zo, nxy), eJ, so_p[1][m]);
+      bstore<double>(plane_rsrc(dA + zo, nxy), eA, so_p[2][0]);
+      bstore<int>(plane_rsrc(dK + zo, nxy), eK, kap_q);
     } else if constexpr (STAGE1) {
       const unsigned ek = on ? out_e : IE;
       const unsigned ec = (on && record_ck) ? out_e : IE;
@@ -534,6 +540,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     T Bp[3] = {T(0), T(0), T(0)};
     double Fzp[3] = {0.0, 0.0, 0.0};
     double rDp = 0.0, Dp = 0.0;
+    int kap_p = 1;
     if (p <= pb1) {
       const int sb = p & 1;
 #pragma unroll
@@ -611,6 +618,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                     if (formed && !(det * want > 0.0)) convex = false;
                   }
                   acc_conc += convex ? 0.0 : 1.0;
+                  kap_p = convex ? 1 : -1;
                 }
               }
             }
@@ -649,6 +657,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
           so_p[0][m] = Bq[m];
           so_p[1][m] = 0.0;  // J: zero on line-tied faces
         }
+        so_p[2][0] = 0.0;
       }
       if (!face) {
         const int o = (ty + 1) * RX1 + (tx + 1);
@@ -682,6 +691,10 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         if constexpr (DIAG) {
 #pragma unroll
           for (int m = 0; m < 3; m++) so_p[1][m] = J[m];
+          // alpha* = J.B / B^2 (Sec. 3.2.1); 0 where B vanishes
+          const double B2 = (double)Bq[0] * Bq[0] + (double)Bq[1] * Bq[1] + (double)Bq[2] * Bq[2];
+          const double JB = (double)J[0] * Bq[0] + (double)J[1] * Bq[1] + (double)J[2] * Bq[2];
+          so_p[2][0] = B2 > 0.0 ? JB / B2 : 0.0;
         }
         const T f0 = J[1] * Bq[2] - J[2] * Bq[1];
         const T f1 = J[2] * Bq[0] - J[0] * Bq[2];
@@ -777,6 +790,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     }
     rDq = rDp;
     Dq = Dp;
+    kap_q = kap_p;
   }
 
   // ---- workgroup reductions -> partial records -----------------------------------------

@@ -1,5 +1,5 @@
-"""IsoHelix set-up and the diagnostics of its relaxed state (Sec. 3.1, 3.2), shared by the
-oracle pin and the GPU accuracy runs.
+"""IsoHelix (and Pontin09) set-ups and the diagnostics of their relaxed states (Sec. 3.1,
+3.2), shared by the oracle pins and the GPU accuracy and breakdown runs.
 
   sigma_B = sqrt(sum |B - B_relax|^2 / N), B_relax = e_z            (eq. "B relaxed"),
   sigma_x = sqrt(sum |x - x_relax|^2 / N), x_relax the rotated grid (eq. "x analytical relaxed"),
@@ -34,17 +34,34 @@ def table1():
     return out
 
 
+def table2():
+    """{n: (xi, eps*)} as the paper prints them (Table 2: Pontin09, mimetic, phi = pi/2)."""
+    out = {}
+    with open(os.path.join(HERE, "golden", "pontin09_table2_mimetic_pi2.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                v = line.split()
+                out[int(v[0])] = tuple(float(a) for a in v[1:])
+    return out
+
+
 def relaxed_state_errors(g, x, B, J):
     """(sigma_B, sigma_x, eps*) of positions x with field B and current J."""
     N = g.N
     sB = math.sqrt(float(((B - np.array([0.0, 0.0, 1.0])[:, None, None, None]) ** 2).sum()) / N)
     sx = math.sqrt(float(((x - W.isohelix_relaxed_map(g, PHI)) ** 2).sum()) / N)
+    alpha = (J * B).sum(axis=0) / (B * B).sum(axis=0)
+    return sB, sx, epsilon_star(g, alpha)
+
+
+def epsilon_star(g, alpha, a_r=AR):
+    """eps* of an alpha* map (nz, ny, nx): the largest a_r |alpha*_i - alpha*_j| / |Z_i - Z_j|
+    over pairs of interior nodes of the central line X = Y = 0 (eq. "epsilon star")."""
     nx, ny, nz = g.n
     i, j = (nx - 1) // 2, (ny - 1) // 2
-    Bl, Jl = B[:, 1:nz - 1, j, i], J[:, 1:nz - 1, j, i]
-    alpha = (Jl * Bl).sum(axis=0) / (Bl * Bl).sum(axis=0)
+    al = alpha[1:nz - 1, j, i]
     Z = g.origin[2] + g.h[2] * np.arange(1, nz - 1)
-    dA = np.abs(alpha[:, None] - alpha[None, :])
+    dA = np.abs(al[:, None] - al[None, :])
     dZ = np.abs(Z[:, None] - Z[None, :])
     np.fill_diagonal(dZ, np.inf)
-    return sB, sx, float(AR * (dA / dZ).max())
+    return float(a_r * (dA / dZ).max())

@@ -8,7 +8,8 @@ the step size drops by orders of magnitude); a finer grid delays the blow-up.  H
 Lambda0 = 1e-7, safety 0.9, dt_min = 1e-9):
   * concave nodes appear long before the end, and their number keeps growing;
   * xi first falls (relaxation), then grows again while E_M, which magneto-friction can only
-    lower, turns upward;
+    lower, turns upward, and eps* (eq. "epsilon star", from the alpha* map of relax_monitors)
+    grows from its minimum by more than an order of magnitude;
   * the run ends with the step size below dt_min (RELAX_E_DT).
 RELAX_BREAKDOWN_FULL=1 also runs 65^3 and checks that the breakdown comes later there.
 """
@@ -19,7 +20,8 @@ import pytest
 
 import paper_1405_0942_amd as R
 import workloads as W
-from gpu_util import banner, context
+from gpu_util import banner, context, host
+from isohelix_util import epsilon_star
 
 pytestmark = pytest.mark.gpu
 
@@ -41,9 +43,11 @@ def run_to_breakdown(n, max_steps):
             if status != R.RELAX_OK:
                 break
             dd = r.diagnostics()
-            rows.append((d[-1]["t"], dd["concave"], dd["xi"], dd["E_M"], dd["min_det"]))
+            alpha, kappa = (host(v) for v in r.monitors())
+            assert int((kappa < 0).sum()) == dd["concave"]
+            rows.append((d[-1]["t"], dd["concave"], dd["xi"], dd["E_M"], dd["min_det"], epsilon_star(g, alpha)))
             banner(f"  n {n}: step {done} t {rows[-1][0]:.2f} concave {rows[-1][1]} xi {rows[-1][2]:.2e} "
-                   f"E_M {rows[-1][3]:.6f} min det {rows[-1][4]:.3e}")
+                   f"E_M {rows[-1][3]:.6f} min det {rows[-1][4]:.3e} eps* {rows[-1][5]:.2e}")
         t_end = r.state()[1]
     return np.array(rows), status, t_end
 
@@ -60,8 +64,12 @@ def test_pontin09_concavity_precedes_breakdown():
     assert xi[i_min] < 0.02 and xi[-1] > 3 * xi[i_min]  # relaxation, then growing force
     j_min = int(np.argmin(E))
     assert j_min < len(E) - 1 and E[-1] > E[j_min] * (1 + 1e-5)  # the energy turns upward
+    eps = rows[:, 5]
+    k_min = int(np.argmin(eps))
+    assert eps[k_min] < 0.5 and eps[-1] > 10 * eps[k_min]  # eps* small, then blows up
     banner(f"  first concave at t {t[first]:.1f}, min xi {xi[i_min]:.2e} at t {t[i_min]:.1f}, "
-           f"E_M minimum at t {t[j_min]:.1f}, breakdown at t {t_end:.2f}")
+           f"min eps* {eps[k_min]:.2e} at t {t[k_min]:.1f}, E_M minimum at t {t[j_min]:.1f}, "
+           f"breakdown at t {t_end:.2f}")
 
 
 @pytest.mark.skipif(os.environ.get("RELAX_BREAKDOWN_FULL") != "1", reason="65^3 run: RELAX_BREAKDOWN_FULL=1")

@@ -87,8 +87,25 @@ def test_concave_count_matches_oracle(case):
     B0 = W.smooth_random_field(g, 0.6, seed=200) + np.array([0.2, -0.1, 1.0])[:, None, None, None]
     with context(g, x0, B0) as r:
         d = r.diagnostics()
-    count = oracle.convexity(g, x0)[1]
+        alpha, kappa = (host(t) for t in r.monitors())
+    okappa, count = oracle.convexity(g, x0)
     assert count > 0 and d["concave"] == count
+    assert np.array_equal(kappa, okappa)
+    assert nrel(alpha, oracle.alpha_star(g, x0, B0)) < 1e-11
+
+
+def test_alpha_star_helical_field_closed_form():
+    """B0 = (sin kZ, cos kZ, 0) on the undistorted periodic grid: alpha* = sin(kh) / h at every
+    node, all nodes convex; either output may be omitted."""
+    banner("alpha* closed form")
+    g = W.make_grid((37, 9, 72), [(0.0, 1.0), (0.0, 1.0), (0.0, 2 * np.pi)], (1, 1, 1))
+    Z = g.coords()[2]
+    B0 = np.stack([np.sin(2 * Z), np.cos(2 * Z), np.zeros_like(Z)])
+    with context(g, g.identity(), B0) as r:
+        alpha, kappa = (host(t) for t in r.monitors())
+        assert R.relax_monitors(r.ctx, 0, 0) == R.RELAX_OK
+    assert np.abs(alpha - np.sin(2 * g.h[2]) / g.h[2]).max() < 1e-12
+    assert np.all(kappa == 1)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])

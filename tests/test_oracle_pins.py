@@ -346,6 +346,17 @@ def test_T13_isohelix_17_relaxed_state_matches_table1():
     assert abs(eps / p[1] - 1) < 0.1 and abs(sB / p[2] - 1) < 0.1 and abs(sx / p[3] - 1) < 0.1, (eps, sB, sx)
 
 
+def test_T13_pontin09_17_relaxed_eps_star_matches_table2():
+    """The oracle relaxes the Pontin09 field (phi = +-pi/2) on the 17^3 grid of Table 2 to the
+    asymptotic eps* the paper prints, within 20 %."""
+    from isohelix_util import epsilon_star, grid, table2
+    g = grid(17)
+    B0 = W.pontin09_field(g, phis=(math.pi / 2, -math.pi / 2))
+    r = oracle.run(g, g.identity(), B0, 2500, dt=1e-3, tol=1e-8, safety=0.9)
+    eps = epsilon_star(g, oracle.alpha_star(g, r["x"], B0))
+    assert abs(eps / table2()[17][1] - 1) < 0.2, eps
+
+
 # --------------------------------------------------------------------------------------
 # T14: convexity (Sec. 3.2.3, eqs. "dx for convexity", "convexity")
 # --------------------------------------------------------------------------------------
@@ -385,6 +396,51 @@ def test_T14_convexity_one_folded_node():
     near = {(k, j, i)} | {(k + dk, j + dj, i + di) for di, dj, dk in
                           [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]}
     assert bad <= near
+
+
+# --------------------------------------------------------------------------------------
+# T15: alpha* (Sec. 3.2.1)
+# --------------------------------------------------------------------------------------
+def _helical(g, k):
+    """B0 = (sin kZ, cos kZ, 0): curl B0 = k B0, a linear force-free field with alpha = k."""
+    X, Y, Z = g.coords()
+    return np.stack([np.sin(k * Z), np.cos(k * Z), np.zeros_like(Z)])
+
+
+@pytest.mark.parametrize("k", [1.0, -2.0])
+def test_T15_alpha_star_helical_field_closed_form(k):
+    """On the undistorted grid B = B0 and the mimetic current reduces to central differences,
+    so J = (sin kh / h) B exactly: alpha* = sin(kh) / h at every node where loops close."""
+    g = W.make_grid((5, 6, 24), [(0.0, 1.0), (0.0, 1.0), (0.0, 2 * math.pi)], (1, 1, 1))
+    a = oracle.alpha_star(g, g.identity(), _helical(g, k))
+    h = g.h[2]
+    assert np.abs(a - math.sin(k * h) / h).max() < 1e-13
+
+
+def test_T15_alpha_star_rotated_grid():
+    """x = R X + b with R a rotation: B and J rotate with the grid and alpha* is unchanged
+    (interior nodes sin(kh)/h as above, 0 on the line-tied faces where J vanishes)."""
+    g = W.make_grid((7, 8, 13), [(-1.0, 1.0), (-1.0, 1.0), (0.0, 3.0)], (0, 0, 0))
+    k = 1.3
+    c, s_ = math.cos(0.7), math.sin(0.7)
+    Rz = np.array([[c, -s_, 0.0], [s_, c, 0.0], [0.0, 0.0, 1.0]])
+    Rx = np.array([[1.0, 0.0, 0.0], [0.0, c, -s_], [0.0, s_, c]])
+    R = Rx @ Rz
+    x = np.einsum("ij,j...->i...", R, g.identity()) + np.array([0.5, -1.0, 2.0])[:, None, None, None]
+    a = oracle.alpha_star(g, x, _helical(g, k))
+    want = np.zeros(g.shape[1:])
+    want[interior(g)] = math.sin(k * g.h[2]) / g.h[2]
+    assert np.abs(a - want).max() < 1e-12
+
+
+def test_T15_alpha_star_sign_and_null():
+    """Reversing B0 leaves alpha* unchanged (J and B both flip); B0 = 0 gives 0, not NaN."""
+    g = W.make_grid((6, 6, 10), [(0.0, 1.0), (0.0, 1.0), (0.0, 2 * math.pi)], (1, 1, 1))
+    x = W.distorted_grid(g, 0.1, seed=3)
+    B0 = _helical(g, 1.0)
+    a = oracle.alpha_star(g, x, B0)
+    assert np.array_equal(a, oracle.alpha_star(g, x, -B0))
+    assert np.all(oracle.alpha_star(g, x, np.zeros_like(B0)) == 0.0)
 
 
 # --------------------------------------------------------------------------------------
