@@ -42,7 +42,8 @@ namespace relax {
 namespace {
 
 __device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
-__device__ __forceinline__ int mod3(int p) { return ((p % 3) + 3) % 3; }
+// p mod 3 in [0, 3) for p >= -3072 (plane indices reach at most three planes below 0)
+__device__ __forceinline__ int mod3(int p) { return (int)((unsigned)(p + 3072) % 3u); }
 
 struct AxisIdx {
   int i, w;
@@ -61,6 +62,16 @@ __device__ __forceinline__ AxisIdx resolve(int v, int n, int bc) {
     r.ok = (v >= 0 && v < n);
   }
   return r;
+}
+
+// resolve() without divisions, exact for v in [-n, 2n): the plane indices of a z march lie
+// within three planes of [0, n) and n >= 4.  Other v give a wrong but in-range index.
+__device__ __forceinline__ AxisIdx resolve_near(int v, int n, int bc) {
+  if (bc == BC_PERIODIC) {
+    const int w = v < 0 ? -1 : (v >= n ? 1 : 0);
+    return AxisIdx{min(max(v - w * n, 0), n - 1), w, true};
+  }
+  return resolve(v, n, bc);
 }
 
 // element index of a masked-off lane (scaled by 8 it lies past every plane's record count)
@@ -145,7 +156,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   __shared__ double gxy[6][RY1 * RX1];    // Gbar'_x (0..2) and Gbar'_y (3..5) of the newest plane
 
   auto zload = [&](int pz) {
-    if (bcz == BC_PERIODIC) return resolve(pz, nz, bcz).i;
+    if (bcz == BC_PERIODIC) return resolve_near(pz, nz, bcz).i;
     return min(max(pz, 0), nz - 1);
   };
 
@@ -220,7 +231,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     }
   };
   auto commit_window = [&](int pz) {
-    const AxisIdx rz = resolve(pz, nz, bcz);
+    const AxisIdx rz = resolve_near(pz, nz, bcz);
     const int slot = mod3(pz);
     const double shz = rz.w * g.period[2];
 #pragma unroll
