@@ -23,14 +23,19 @@ def grid(n):
     return W.make_grid((n, n, n), [(-4.0, 4.0), (-4.0, 4.0), (-10.0, 10.0)], (0, 0, 0))
 
 
-def table1():
-    """{n: (xi, eps*, sigma_B, sigma_x)} as the paper prints them (Table 1, mimetic, phi = pi/4)."""
+PHIS = {"pi/4": math.pi / 4, "pi/2": math.pi / 2, "pi": math.pi}
+
+
+def table1(phi="pi/4"):
+    """{n: (xi, eps*, sigma_B, sigma_x), or None for a run that did not converge} as the paper
+    prints them (Table 1, mimetic rows of twist angle phi: "pi/4", "pi/2" or "pi")."""
     out = {}
-    with open(os.path.join(HERE, "golden", "isohelix_table1_mimetic_pi4.txt")) as f:
+    with open(os.path.join(HERE, "golden", "isohelix_table1_mimetic.txt")) as f:
         for line in f:
             if line.strip() and not line.startswith("#"):
                 v = line.split()
-                out[int(v[0])] = tuple(float(a) for a in v[1:])
+                if v[0] == phi:
+                    out[int(v[1])] = None if v[2] == "--" else tuple(float(a) for a in v[2:])
     return out
 
 
@@ -45,11 +50,12 @@ def table2():
     return out
 
 
-def relaxed_state_errors(g, x, B, J):
-    """(sigma_B, sigma_x, eps*) of positions x with field B and current J."""
+def relaxed_state_errors(g, x, B, J, phi=PHI):
+    """(sigma_B, sigma_x, eps*) of positions x with field B and current J (IsoHelix of twist
+    angle phi)."""
     N = g.N
     sB = math.sqrt(float(((B - np.array([0.0, 0.0, 1.0])[:, None, None, None]) ** 2).sum()) / N)
-    sx = math.sqrt(float(((x - W.isohelix_relaxed_map(g, PHI)) ** 2).sum()) / N)
+    sx = math.sqrt(float(((x - W.isohelix_relaxed_map(g, phi)) ** 2).sum()) / N)
     alpha = (J * B).sum(axis=0) / (B * B).sum(axis=0)
     return sB, sx, epsilon_star(g, alpha)
 

@@ -97,6 +97,7 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
     assert R.lib().relax_diagnostics(None, None) == R.RELAX_E_ARG
     assert R.lib().relax_velocity(None, None) == R.RELAX_E_ARG
     assert R.lib().relax_fields(None, None, None) == R.RELAX_E_ARG
+    assert R.lib().relax_monitors(None, None, None) == R.RELAX_E_ARG
     assert R.relax_last_error(None) == ""
     R.relax_destroy(None)
 

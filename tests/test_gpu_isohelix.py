@@ -1,15 +1,19 @@
-"""IsoHelix accuracy runs (Sec. 3.1, 3.2; the mimetic rows of Table 1, phi = pi/4, FP64).
+"""IsoHelix accuracy runs (Sec. 3.1, 3.2; the mimetic rows of Table 1, FP64).
 
-The IsoHelix field (eq. "B init analytical": B0 = 1, a_r = sqrt 2, a_z = 2) on odd vertex grids
-n^3 over [-4, 4]^2 x [-10, 10], all faces line-tied, x0 = X, relaxed with the adaptive step
-(Lambda0 = 1e-8, safety 0.9) until sigma_B and sigma_x settle (1e-3 over two chunks); B and J of the relaxed state
-come from relax_fields (checked against the oracle's fields of the same positions).
+The IsoHelix field (eq. "B init analytical": B0 = 1, a_r = sqrt 2, a_z = 2) of twist angle
+phi = pi/4, pi/2 or pi on odd vertex grids n^3 over [-4, 4]^2 x [-10, 10], all faces
+line-tied, x0 = X, relaxed with the adaptive step (Lambda0 = 1e-8, safety 0.9, dt_min 1e-9)
+until sigma_B and sigma_x settle (1e-3 over two chunks); B and J of the relaxed state come
+from relax_fields (checked against the oracle's fields of the same positions).
 
 sigma_B, sigma_x and eps* (definitions in isohelix_util) are compared with the values the
-paper prints in Table 1 (tests/golden/isohelix_table1_mimetic_pi4.txt) within 30 %, and
-must fall with resolution as the paper reports.  xi is not compared: it keeps falling with
-the run length and depends on Lambda0 (the paper says so, Sec. 4.1), neither of which the
-paper states; it must only show that the field relaxed.  RELAX_ISOHELIX_FULL=1 adds n = 129.
+paper prints in Table 1 (tests/golden/isohelix_table1_mimetic.txt) within 30 %, and must
+fall with resolution as the paper reports for phi = pi/4.  Where the paper marks a run as not
+converging (phi = pi, n = 17) the run must end in the step-size collapse.  The paper ran the
+pi/2 and pi rows in single precision; these runs are FP64.  xi is not compared: it keeps
+falling with the run length and depends on Lambda0 (the paper says so, Sec. 4.1), neither of
+which the paper states; it must only show that the field relaxed.  RELAX_ISOHELIX_FULL=1 adds
+n = 129.
 """
 import os
 
@@ -17,9 +21,10 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_1405_0942_amd as R
 import workloads as W
 from gpu_util import banner, context, host, nrel
-from isohelix_util import PHI, grid, relaxed_state_errors, table1
+from isohelix_util import PHIS, grid, relaxed_state_errors, table1
 
 pytestmark = pytest.mark.gpu
 
@@ -30,18 +35,22 @@ if not torch.cuda.is_available():  # pragma: no cover
 SIZES = (17, 33, 65, 129) if os.environ.get("RELAX_ISOHELIX_FULL") == "1" else (17, 33, 65)
 
 
-def relax(n, max_steps=200_000):
+def relax(n, phi, max_steps=200_000):
+    """(grid, B0, x, B, J, final diagnostics, steps, status) of a run to the relaxed state."""
     g = grid(n)
-    B0 = W.isohelix_field(g, PHI)
-    with context(g, g.identity(), B0, dt0=1e-3, tol=1e-8, safety=0.9) as r:
+    B0 = W.isohelix_field(g, phi)
+    with context(g, g.identity(), B0, dt0=1e-3, tol=1e-8, safety=0.9, dt_min=1e-9) as r:
         done, chunk, hist = 0, 250, []
         while done < max_steps:
-            d = r.step(chunk)
+            d = r.step(chunk, raise_on_error=False)
             done += len(d)
+            if r.last_status != R.RELAX_OK:
+                banner(f"  n {n}: status {r.last_status} after {done} steps")
+                return g, B0, None, None, None, None, done, r.last_status
             x = host(r.state()[0])
             Bt, Jt = r.fields()
             B, J = host(Bt), host(Jt)
-            sB, sx, eps = relaxed_state_errors(g, x, B, J)
+            sB, sx, eps = relaxed_state_errors(g, x, B, J, phi)
             hist.append((sB, sx))
             banner(f"  n {n}: step {done}, t {d[-1]['t']:.1f}, dt {d[-1]['dt']:.3e}, xi {d[-1]['xi']:.2e}, "
                    f"sigma_B {sB:.3e}, sigma_x {sx:.3e}, eps* {eps:.2e}")
@@ -49,27 +58,26 @@ def relax(n, max_steps=200_000):
                 break
             chunk = min(2 * chunk, 16_000)
         fin = r.diagnostics()
-    return g, B0, x, B, J, fin, done
+    return g, B0, x, B, J, fin, done, R.RELAX_OK
 
 
-@pytest.fixture(scope="module")
-def runs():
-    out = {}
-    for n in SIZES:
-        banner(f"IsoHelix phi = pi/4, {n}^3, FP64")
-        out[n] = relax(n)
-    return out
-
-
-def test_isohelix_relaxed_state_matches_table1(runs):
-    paper = table1()
+@pytest.mark.parametrize("phi", ["pi/4", "pi/2", "pi"])
+def test_isohelix_relaxed_state_matches_table1(phi):
+    paper = table1(phi)
     table = {}
-    for n, (g, B0, x, B, J, fin, steps) in runs.items():
-        sB, sx, eps = relaxed_state_errors(g, x, B, J)
+    for n in SIZES:
+        banner(f"IsoHelix phi = {phi}, {n}^3, FP64")
+        g, B0, x, B, J, fin, steps, status = relax(n, PHIS[phi])
+        p = paper[n]
+        if p is None:  # the paper's run did not converge
+            assert status == R.RELAX_E_DT, status
+            banner(f"n {n}: breaks down after {steps} steps | Table 1: no converged values")
+            continue
+        assert status == R.RELAX_OK
+        sB, sx, eps = relaxed_state_errors(g, x, B, J, PHIS[phi])
         table[n] = (fin["xi"], eps, sB, sx)
         o = oracle.fields(g, x, B0)
         assert nrel(B, o["B"]) < 1e-12 and nrel(J, o["J"]) < 1e-11
-        p = paper[n]
         banner(f"n {n}: xi {fin['xi']:.2e} eps* {eps:.2e} sigma_B {sB:.2e} sigma_x {sx:.2e} ({steps} steps) | "
                f"Table 1: eps* {p[1]:.1e} sigma_B {p[2]:.1e} sigma_x {p[3]:.1e}")
         for k in (1, 2, 3):
@@ -78,5 +86,6 @@ def test_isohelix_relaxed_state_matches_table1(runs):
     ns = sorted(table)
     for a, b in zip(ns, ns[1:]):
         assert table[b][2] < 0.5 * table[a][2]  # sigma_B falls with resolution
-        assert table[b][3] <= 1.05 * table[a][3]  # sigma_x does not grow
         assert table[b][1] < table[a][1]  # eps* falls with resolution
+        if phi == "pi/4":
+            assert table[b][3] <= 1.05 * table[a][3]  # sigma_x does not grow

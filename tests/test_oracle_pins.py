@@ -346,6 +346,18 @@ def test_T13_isohelix_17_relaxed_state_matches_table1():
     assert abs(eps / p[1] - 1) < 0.1 and abs(sB / p[2] - 1) < 0.1 and abs(sx / p[3] - 1) < 0.1, (eps, sB, sx)
 
 
+def test_T13_isohelix_pi_17_does_not_converge():
+    """Table 1 marks the mimetic IsoHelix run with phi = pi on the 17^3 grid as not
+    converging; the oracle's run breaks down (step size below dt_min) within 1000 steps."""
+    import math
+    from isohelix_util import grid, table1
+    assert table1("pi")[17] is None
+    g = grid(17)
+    B0 = W.isohelix_field(g, math.pi)
+    r = oracle.run(g, g.identity(), B0, 1000, dt=1e-3, tol=1e-8, safety=0.9, dt_min=1e-9, raise_on_error=False)
+    assert r["status"] == oracle.E_DT and r["done"] < 1000, (r["status"], r["done"])
+
+
 def test_T13_pontin09_17_relaxed_eps_star_matches_table2():
     """The oracle relaxes the Pontin09 field (phi = +-pi/2) on the 17^3 grid of Table 2 to the
     asymptotic eps* the paper prints, within 20 %."""
