@@ -109,18 +109,31 @@ bool valid_config(const relax_config* c) {
   return true;
 }
 
-// z-chunk length: about one round of resident workgroups (2 per CU on 256 CUs), chunks of
-// >= 16 planes so the extra stage-input planes at each chunk start stay a small overhead
+// z-chunk length.  A sweep's workgroups march their chunks concurrently, two resident per CU
+// on 256 CUs (512 slots), so a sweep takes about ceil(workgroups / 512) rounds, each as long
+// as one chunk: tz planes plus the ~4 planes a chunk loads before its first output.  The
+// chunk count minimises rounds x (tz + 4) with tz >= 16 (the fewer chunks on a tie): a grid
+// whose x-y tiles alone slightly exceed the slots (384^3: 576 tiles) would otherwise run a
+// second, nearly empty round as long as the first.
 int choose_tz(const relax_config* c, int tiles_xy) {
   if (const char* e = std::getenv("RELAX_TZ")) {
     int v = std::atoi(e);
     if (v >= 1) return std::min(v, c->n[2]);
   }
-  const int target_blocks = 512;
-  int chunks = std::max(1, (target_blocks + tiles_xy - 1) / tiles_xy);
-  int tz = (c->n[2] + chunks - 1) / chunks;
-  tz = std::max(tz, 16);
-  return std::min(tz, c->n[2]);
+  const long long slots = 512;
+  const int nz = c->n[2];
+  int best_tz = nz;
+  long long best_cost = -1;
+  for (int chunks = 1; chunks <= std::max(1, nz / 16); chunks++) {
+    const int tz = (nz + chunks - 1) / chunks;
+    const long long blocks = (long long)tiles_xy * ((nz + tz - 1) / tz);
+    const long long cost = ((blocks + slots - 1) / slots) * (tz + 4);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best_tz = tz;
+    }
+  }
+  return best_tz;
 }
 
 Geometry make_geometry(const relax_config* c) {
