@@ -78,6 +78,12 @@ def test_workspace_bytes_valid_and_invalid():
     for sf in (0.0, 1.5, float("nan")):
         assert R.relax_workspace_bytes(_cfg(safety=sf)) == 0
     assert R.relax_workspace_bytes(_cfg(), -1) == 0
+    # plane size limit: n[0] * n[1] < 2^28 (32-bit buffer offsets within a plane)
+    big = _cfg()
+    big.n[0], big.n[1], big.n[2] = 1 << 14, 1 << 14, 4
+    assert R.relax_workspace_bytes(big) == 0
+    big.n[1] = (1 << 14) - 1
+    assert R.relax_workspace_bytes(big) >= 11 * 3 * big.n[0] * big.n[1] * 4 * 8
 
 
 def test_init_rejects_bad_arguments_without_touching_the_gpu():
