@@ -317,6 +317,58 @@ def test_full_size_braid_one_step_all_nodes():
     assert rel(diag[0]["xi"], o["diag"][0, 3]) < 1e-11
 
 
+def _jacobian_host(g, x):
+    """F[i][j] = dx_i/dX_j (9, nz, ny, nx) by central differences; periodic axes wrap with
+    the coordinate shift of that axis, line-tied ends take second-order one-sided rows."""
+    F = np.empty((3, 3) + x.shape[1:])
+    for j, ax in ((0, 3), (1, 2), (2, 1)):
+        h, n = g.h[j], g.n[j]
+        if g.bc[j] == W.PERIODIC:
+            up, dn = np.roll(x, -1, axis=ax), np.roll(x, 1, axis=ax)
+            sl_hi = [slice(None)] * 4
+            sl_hi[ax] = n - 1
+            sl_lo = [slice(None)] * 4
+            sl_lo[ax] = 0
+            up[tuple([j] + sl_hi[1:])] += n * h  # x(n) is the image of x(0) shifted by the period
+            dn[tuple([j] + sl_lo[1:])] -= n * h
+            d = (up - dn) / (2 * h)
+        else:
+            d = np.empty_like(x)
+            mid = [slice(None)] * 4
+            mid[ax] = slice(1, -1)
+            a = [slice(None)] * 4
+            b = [slice(None)] * 4
+            a[ax], b[ax] = slice(2, None), slice(None, -2)
+            d[tuple(mid)] = (x[tuple(a)] - x[tuple(b)]) / (2 * h)
+            for end, (i0, i1, i2, sgn) in ((0, (0, 1, 2, 1.0)), (n - 1, (n - 1, n - 2, n - 3, -1.0))):
+                s0, s1, s2, se = ([slice(None)] * 4 for _ in range(4))
+                s0[ax], s1[ax], s2[ax], se[ax] = i0, i1, i2, end
+                d[tuple(se)] = sgn * (-3 * x[tuple(s0)] + 4 * x[tuple(s1)] - x[tuple(s2)]) / (2 * h)
+        for i in range(3):
+            F[i, j] = d[i]
+    return F
+
+
+def test_full_size_material_flux_invariant():
+    """Frozen-in flux (Sec. 2.1, eq. "B transformation"): through every material face element
+    B . cof(F) e_q = B0_q exactly, whatever the grid.  Checked at every node of the 128x128x384
+    braid after 300 adaptive steps, with F formed on the host from the GPU's positions."""
+    banner("braid 128x128x384: material flux at every node after 300 steps")
+    w = W.braid(128, 384)
+    with context(w.grid, w.x0, w.B0, dt0=w.dt0, tol=w.tol) as r:
+        r.step(300, diag=False)
+        x = host(r.state()[0])
+        B = host(r.fields()[0])
+    F = _jacobian_host(w.grid, x)
+    assert float(np.abs(x - w.x0).max()) > 1e-2  # the grid has moved
+    for q in range(3):
+        a, b = (q + 1) % 3, (q + 2) % 3
+        cof = np.cross(F[:, a], F[:, b], axis=0)  # cof(F) e_q = F e_a x F e_b
+        flux = (B * cof).sum(axis=0)
+        assert np.abs(flux - w.B0[q]).max() < 1e-12 * np.abs(w.B0).max(), q
+    del F
+
+
 def test_abc_256_undistorted_fixed_point():
     """At any size the undistorted ABC box is a discrete equilibrium (u = 0 to rounding)."""
     banner("abc 256^3 undistorted fixed point")
