@@ -445,13 +445,15 @@ def test_T15_alpha_star_rotated_grid():
     assert np.abs(a - want).max() < 1e-12
 
 
-def test_T15_alpha_star_sign_and_null():
-    """Reversing B0 leaves alpha* unchanged (J and B both flip); B0 = 0 gives 0, not NaN."""
+def test_T15_alpha_star_sign_scale_and_null():
+    """Reversing B0 leaves alpha* unchanged (J and B both flip), and so does scaling it
+    (J.B and B^2 both scale with its square); B0 = 0 gives 0, not NaN."""
     g = W.make_grid((6, 6, 10), [(0.0, 1.0), (0.0, 1.0), (0.0, 2 * math.pi)], (1, 1, 1))
     x = W.distorted_grid(g, 0.1, seed=3)
     B0 = _helical(g, 1.0)
     a = oracle.alpha_star(g, x, B0)
     assert np.array_equal(a, oracle.alpha_star(g, x, -B0))
+    assert np.abs(oracle.alpha_star(g, x, 2.5 * B0) - a).max() < 1e-13 * np.abs(a).max()
     assert np.all(oracle.alpha_star(g, x, np.zeros_like(B0)) == 0.0)
 
 
