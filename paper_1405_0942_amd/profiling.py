@@ -88,6 +88,29 @@ def traffic(fetch_dir: str, write_dir: str, mixed: bool):
     return out, f_scale, w_scale
 
 
+def sq_counters(run_dirs, mixed: bool):
+    """{stage: {counter: median over the launches of that stage}} from `--pmc SQ_...` runs
+    (the median keeps the stage-1 launches of retried attempts, which exit at once and are
+    a minority, out of the figure)."""
+    per = collections.defaultdict(lambda: collections.defaultdict(dict))  # stage -> dispatch -> counter
+    for d in run_dirs:
+        with open(_counter_csv(d), newline="") as f:
+            for r in csv.DictReader(f):
+                st = _stage_of(r["Kernel_Name"])
+                if st is None or st[1] != mixed:
+                    continue
+                disp = per[st[0]][(d, int(r["Dispatch_Id"]))]
+                disp[r["Counter_Name"]] = disp.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    out = {}
+    for s, disps in sorted(per.items()):
+        cols = collections.defaultdict(list)
+        for vals in disps.values():
+            for c, v in vals.items():
+                cols[c].append(v)
+        out[s] = {c: sorted(v)[len(v) // 2] for c, v in cols.items()}
+    return out
+
+
 def read_traffic(path: str):
     """key: value lines of a traffic summary, or None if there is no such file."""
     if not os.path.exists(path):
@@ -135,8 +158,32 @@ def main(argv=None):
     t.add_argument("--precision", choices=["fp64", "fp32-mixed"], default="fp64")
     t.add_argument("--nodes", type=int, required=True, help="grid nodes (for bytes per node)")
     t.add_argument("--command", required=True, help="the profiled command, recorded in the summary")
+    q = sub.add_parser("sq")
+    q.add_argument("--run", action="append", required=True, help="rocprofv3 output directory of a --pmc run")
+    q.add_argument("--workload", required=True)
+    q.add_argument("--precision", choices=["fp64", "fp32-mixed"], default="fp64")
+    q.add_argument("--nodes", type=int, required=True, help="grid nodes (counts are per 64 nodes)")
+    q.add_argument("--command", required=True, help="the profiled commands, recorded in the summary")
     args = ap.parse_args(argv)
     w = sys.stdout.write
+    if args.cmd == "sq":
+        per = sq_counters(args.run, args.precision == "fp32-mixed")
+        cols = sorted({c for v in per.values() for c in v})
+        w(f"# SQ counters per launch of the stage sweeps, {args.workload}, {args.precision}\n\n")
+        w("Commands (from the repository root):\n\n")
+        w(f"    {args.command}\n\n")
+        w(f"Median over launches; instruction counts are per 64 grid nodes (one wave's worth), "
+          f"SQ_WAVES and cycle counts per launch.\n\n")
+        w(f"source_sha256: {kernel_source_hash()}\n\n")
+        w("| stage | " + " | ".join(cols) + " |\n|---|" + "---:|" * len(cols) + "\n")
+        batches = args.nodes / 64.0
+        for s_, v in per.items():
+            cells = []
+            for c in cols:
+                x = v.get(c, float("nan"))
+                cells.append(f"{x / batches:.1f}" if c.startswith("SQ_INSTS") else f"{x:.4g}")
+            w(f"| {s_} | " + " | ".join(cells) + " |\n")
+        return
     if args.cmd == "kernel-stats":
         w(f"# {args.title}\n\n")
         w("Command (from the repository root):\n\n")
