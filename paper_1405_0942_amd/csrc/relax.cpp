@@ -109,22 +109,23 @@ bool valid_config(const relax_config* c) {
   return true;
 }
 
-// z-chunk length.  A sweep's workgroups march their chunks concurrently, two resident per CU
-// on 256 CUs (512 slots), so a sweep takes about ceil(workgroups / 512) rounds, each as long
-// as one chunk: tz planes plus the ~4 planes a chunk loads before its first output.  The
-// chunk count minimises rounds x (tz + 4) with tz >= 16 (the fewer chunks on a tie): a grid
-// whose x-y tiles alone slightly exceed the slots (384^3: 576 tiles) would otherwise run a
-// second, nearly empty round as long as the first.
+// z-chunk length.  A sweep's workgroups march their chunks concurrently, one resident per CU
+// on 256 CUs (256 slots: 91 KB of LDS in FP64, and the mixed sweeps' registers leave room for
+// one 8-wave workgroup), so a sweep takes about ceil(workgroups / 256) rounds, each as long as
+// one chunk: tz planes plus the ~4 planes a chunk loads before its first output.  The chunk
+// count minimises rounds x (tz + 4) with tz >= 8 (the fewer chunks on a tie): a grid whose
+// x-y tiles alone slightly exceed the slots would otherwise run a second, nearly empty round
+// as long as the first, and a small grid would leave most CUs idle.
 int choose_tz(const relax_config* c, int tiles_xy) {
   if (const char* e = std::getenv("RELAX_TZ")) {
     int v = std::atoi(e);
     if (v >= 1) return std::min(v, c->n[2]);
   }
-  const long long slots = 512;
+  const long long slots = 256;
   const int nz = c->n[2];
   int best_tz = nz;
   long long best_cost = -1;
-  for (int chunks = 1; chunks <= std::max(1, nz / 16); chunks++) {
+  for (int chunks = 1; chunks <= std::max(1, nz / 8); chunks++) {
     const int tz = (nz + chunks - 1) / chunks;
     const long long blocks = (long long)tiles_xy * ((nz + tz - 1) / tz);
     const long long cost = ((blocks + slots - 1) / slots) * (tz + 4);

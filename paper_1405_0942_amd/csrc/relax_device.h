@@ -14,8 +14,8 @@ namespace relax {
 // and marches up a z-chunk of TZ planes; one wave64 covers one x-row of the tile.
 // ------------------------------------------------------------------------------------------
 constexpr int TX = 64;
-constexpr int TY = 4;
-constexpr int NTHREADS = TX * TY;  // 256 = 4 waves
+constexpr int TY = 8;
+constexpr int NTHREADS = TX * TY;  // 512 = 8 waves; one workgroup per CU (LDS: 91 KB in FP64)
 constexpr int RX2 = TX + 4, RY2 = TY + 4;  // stage-input window (2-node halo)
 constexpr int RX1 = TX + 2, RY1 = TY + 2;  // pulled-back field window (1-node halo)
 constexpr int NPART = 8;                   // doubles per workgroup partial record
