@@ -30,7 +30,7 @@
 // det F |f|^2 dV enters through ubar = det F dV f / gamma (read from a buffer) plus
 // 1/2 |f|^2 dV / (8 hx hy hz) on Dbar'.
 //
-// The field sweep is laid out like the forward stage sweep: a 64 x 4 tile marching up a
+// The field sweep is laid out like the forward stage sweep: a 64 x 8 tile marching up a
 // z-chunk, the stage input in an LDS ring of three planes (stages 3..6 stencil the stored
 // y_s of the step), B in a ring of two planes, Gbar'_x and Gbar'_y in one plane that is
 // transposed in-plane as soon as it is formed; buffer loads with masked-off lanes (offsets

@@ -31,7 +31,7 @@
 // halos; the k_j they still need are read at the output node only.  A retried step
 // (smaller dt, same x_n and k_1) starts again at stage 2, which rebuilds y_2 and y_3.
 //
-// Data flow: a workgroup owns a 64 x 4 (x, y) tile and marches up a z-chunk.  Each plane
+// Data flow: a workgroup owns a 64 x 8 (x, y) tile and marches up a z-chunk.  Each plane
 // of the stage input (tile + 2-node halo, FP64) goes into an LDS ring of three planes;
 // F', det F' and B are formed on the tile + 1-node halo into an LDS ring of two B planes
 // (the z difference of B at the tile node uses the node's own B of the neighbouring
