@@ -16,17 +16,19 @@ CFLAGS = ["-O2", "-std=c99", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", 
           "-Wno-unused-function", "-Wno-unused-macros"]
 
 
-def build(verbose: bool = False, sanitize: bool = False) -> str:
-    extra = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"] if sanitize else []
+def build(verbose: bool = False, sanitize: bool = False, out: str | None = None) -> str:
+    extra = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"] \
+        if sanitize else []
     objs = []
     for tag, defs in (("r", []), ("z", ["-DORACLE_COMPLEX"])):
-        obj = os.path.join(HERE, f"oracle_{tag}.o")
+        obj = os.path.join(os.path.dirname(out) if out else HERE, f"oracle_{tag}{'_asan' if sanitize else ''}.o")
         cmd = ["gcc", *CFLAGS, *extra, *defs, "-c", SRC, "-o", obj]
         if verbose:
             print(" ".join(cmd))
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    out = LIB if not sanitize else os.path.join(HERE, "liboracle_asan.so")
+    if out is None:
+        out = LIB if not sanitize else os.path.join(HERE, "liboracle_asan.so")
     cmd = ["gcc", "-shared", "-fopenmp", *extra, *objs, "-o", out + ".tmp", "-lm"]
     if verbose:
         print(" ".join(cmd))

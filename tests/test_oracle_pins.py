@@ -520,6 +520,44 @@ def test_T12_brute_force_8cubed(bc):
 
 
 # --------------------------------------------------------------------------------------
+# The sampled right-hand side (spot checks of full-size grids) pulls B back at the loop
+# vertices on the spot and decomposes flat node indices itself: against the brute-force
+# evaluation on ragged grids small enough for it, and against the pinned full sweep on
+# ragged grids (nx, ny, nz all different, so a transposed index shows) of every boundary mix
+# --------------------------------------------------------------------------------------
+BC_MIXES = [tuple(int(b) for b in f"{m:03b}"[::-1]) for m in range(8)]
+
+
+def _ragged_case(n, bc, seed):
+    g = W.make_grid(n, [(-1.0, 1.1), (-0.6, 0.9), (0.0, 1.7)], bc)
+    x = W.distorted_grid(g, 0.08 * min(g.h), seed=seed)
+    B0 = W.smooth_random_field(g, 1.0, seed=seed + 1) + np.array([0.3, -0.2, 1.2])[:, None, None, None]
+    return g, x, B0
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 1), (1, 1, 1)])
+def test_rhs_sampled_matches_brute_force(bc):
+    g, x, B0 = _ragged_case((7, 5, 6), bc, seed=41)
+    r = brute.rhs(g, x, B0)
+    nodes = np.arange(g.N)
+    us = oracle.rhs_sampled(g, x, B0, nodes)
+    assert nrel(us, r["u"].reshape(3, -1).T) < 1e-13
+
+
+@pytest.mark.parametrize("bc", BC_MIXES, ids=["".join(map(str, b)) for b in BC_MIXES])
+def test_rhs_sampled_matches_full_sweep(bc):
+    g, x, B0 = _ragged_case((13, 9, 11), bc, seed=43)
+    u = oracle.fields(g, x, B0, gamma=0.7)["u"].reshape(3, -1)
+    rng = np.random.default_rng(44)
+    corners = [((k * g.n[1]) + j) * g.n[0] + i for i in (0, 1, g.n[0] - 1) for j in (0, 1, g.n[1] - 1)
+               for k in (0, 1, g.n[2] - 1)]
+    nodes = np.concatenate([rng.permutation(g.N), corners])
+    us = oracle.rhs_sampled(g, x, B0, nodes, gamma=0.7)
+    assert np.abs(u).max() > 0.0
+    assert nrel(us, u[:, nodes].T) < 1e-14
+
+
+# --------------------------------------------------------------------------------------
 # Diagnostics: closed forms for E_M; xi and R2 from a library curl on the undistorted grid
 # --------------------------------------------------------------------------------------
 @pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0), (1, 1, 1)])
