@@ -10,8 +10,11 @@ device step control; rejected attempts are redone inside and counted in the time
 
 Prints one JSON line.  value = N * accepted steps / wall time of the timed relax_step
 call (inputs resident in HBM), FP64.  The FP32-mixed figures are in "fp32_mixed".
-"roofline" is the dominant kernel's algorithmic bytes per launch over its average launch
-duration (HIP events around each launch), against the 8 TB/s HBM3E peak.
+"roofline" is the dominant kernel's algorithmic bytes per launch (the stage-fused step's
+compulsory traffic per node, 72..192 B FP64 / 48..120 B FP32-mixed, times the nodes) over its
+average launch duration (HIP events around each launch on the library's stream), against the
+8 TB/s HBM3E peak; config.step_hbm_frac is the same for the whole step (792 / 480 B per node
+per accepted step over the wall time per step, rejected attempts included in the time).
 """
 from __future__ import annotations
 
@@ -29,19 +32,26 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 METRIC = "grid-point updates/s (FP64 vs FP32-mixed) + % HBM roofline at 256^3"
 
-# algorithmic HBM bytes per node of each stage sweep.  Both modes:
+# Algorithmic HBM bytes per node of the stage-fused Cash-Karp step (compulsory traffic, halo
+# re-reads served by the caches): stage s = 1..5 reads x_n, k_1..k_{s-1} and B0 and writes
+# k_s; stage 6 reads x_n, k_1..k_5 and B0 and writes x_{n+1}.  FP64: every vector 24 B;
+# FP32-mixed: x in FP64 (24 B), B0 and the k_j in FP32 (12 B).  Per accepted step 792 / 480 B.
+ALGO_FP64 = [72, 96, 120, 144, 168, 192]
+ALGO_MIXED = [48, 60, 72, 84, 96, 120]
+ALGO_STEP = {"fp64": sum(ALGO_FP64), "fp32-mixed": sum(ALGO_MIXED)}
+
+# What this library's sweeps move per node (its own design, used only for the "design" keys):
+# stages 2..5 also store the next stage input y_{s+1}; in FP64 stage 4 stores the partial sums
+# Y6, dX, E that stages 5 and 6 read instead of k_1..k_4.
 #   stage 1: x_n, B0 -> k_1
 #   stage 2: x_n, k_1, B0, k_1 at the node -> k_2, y_3
 #   stage 3: y_3, B0, k_1, k_2 at the node -> k_3, y_4
-# FP64 (every vector 24 B):
-#   stage 4: y_4, B0, k_1..k_3 at the node -> y_5 and the sums Y6, dX, E
-#   stage 5: y_5, B0, Y6 and E at the node -> y_6, E
-#   stage 6: y_6, B0, x_n, dX and E at the node -> x_{n+1}
-# FP32-mixed (x_n, y_s in FP64; k_j and B0 in FP32):
-#   stage s = 4, 5: y_s, B0, k_1..k_{s-1} at the node -> k_s, y_{s+1}
-#   stage 6: y_6, B0, x_n, k_1, k_3, k_4, k_5 at the node -> x_{n+1}
-BYTES_FP64 = [72, 144, 144, 216, 144, 144]
-BYTES_MIXED = [48, 96, 96, 108, 120, 132]
+# FP64: stage 4: y_4, B0, k_1..k_3 -> y_5, Y6, dX, E; stage 5: y_5, B0, Y6, E -> y_6, E;
+#       stage 6: y_6, B0, x_n, dX, E -> x_{n+1}
+# FP32-mixed: stage s = 4, 5: y_s, B0, k_1..k_{s-1} -> k_s, y_{s+1};
+#       stage 6: y_6, B0, x_n, k_1, k_3, k_4, k_5 -> x_{n+1}
+DESIGN_FP64 = [72, 144, 144, 216, 144, 144]
+DESIGN_MIXED = [48, 96, 96, 108, 120, 132]
 
 
 def log(msg):
@@ -53,14 +63,15 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
     x0 = torch.from_numpy(w.x0).cuda()
     B0 = torch.from_numpy(w.B0).cuda()
     N = w.grid.N
+    tag = "fp64" if precision == R.RELAX_FP64 else "fp32-mixed"
     out = {}
     with R.Relaxation(cfg, x0, B0) as r:
         del x0, B0
-        log(f"precision {precision}: warmup {warmup} steps")
+        log(f"{tag}: warmup {warmup} steps")
         r.step(warmup, diag=False)
         torch.cuda.synchronize()
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        log(f"precision {precision}: timed {steps} steps")
+        log(f"{tag}: timed {steps} steps")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         start.record(r.stream)
@@ -70,32 +81,37 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
         wall = time.perf_counter() - t0
         ev_ms = start.elapsed_time(stop)
         rejects = sum(d["rejects"] for d in diag)
-        # second pass with every launch bracketed by HIP events, for the per-kernel figures
-        log(f"precision {precision}: profiled {steps} steps")
+        # second pass with every launch bracketed by HIP events on the library's stream
+        log(f"{tag}: profiled {steps} steps")
         r.profile(True)
         r.step(steps, diag=False)
         prof = r.profile(False)
-        fin = r.diagnostics()
-    bytes_node = BYTES_FP64 if precision == R.RELAX_FP64 else BYTES_MIXED
+    algo = ALGO_FP64 if precision == R.RELAX_FP64 else ALGO_MIXED
+    design = DESIGN_FP64 if precision == R.RELAX_FP64 else DESIGN_MIXED
     kernels = {}
-    for s in range(2, 7):  # stage 1 is skipped on retries, so its launch count overstates work
+    for s in range(1, 7):
         ms, n = prof[f"stage{s}"]
-        avg = ms / n
-        gbs = bytes_node[s - 1] * N / (avg * 1e-3) / 1e9
-        kernels[f"stage{s}"] = {"avg_ms": avg, "launches": n, "GB/s": gbs}
-    ms1, n1 = prof["stage1"]
-    kernels["stage1"] = {"total_ms": ms1, "launches": n1}
+        if n == 0:
+            continue
+        # stage 1 is skipped (an early exit) on retried attempts; its time is spread over the
+        # accepted steps, which are the launches that do its work
+        work = steps if s == 1 else n
+        avg = ms / work
+        kernels[f"stage{s}"] = {"avg_ms": avg, "launches": n, "working_launches": work, "total_ms": ms,
+                                "algorithmic_GBs": algo[s - 1] * N / (avg * 1e-3) / 1e9,
+                                "design_GBs": design[s - 1] * N / (avg * 1e-3) / 1e9}
     kernels["control"] = {"total_ms": prof["control"][0], "launches": prof["control"][1]}
-    dom = max((k for k in kernels if "avg_ms" in kernels[k]), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-    achieved = kernels[dom]["GB/s"]
-    tag = "fp64" if precision == R.RELAX_FP64 else "fp32-mixed"
-    traffic = measured_traffic(int(dom[-1]), tag, w.name.replace("^3", ""))
-    # bytes per accepted step, rejected attempts included: each stage's bytes times its
-    # launches per accepted step in the profiled pass (stage 1 runs once per accepted step)
-    step_bytes = sum(bytes_node[s - 1] * (prof[f"stage{s}"][1] if s > 1 else steps) for s in range(1, 7)) / steps * N
+    dom = max((k for k in kernels if "avg_ms" in kernels[k]), key=lambda k: kernels[k]["total_ms"])
+    stage = int(dom[-1])
+    achieved = kernels[dom]["algorithmic_GBs"]
+    traffic = measured_traffic(stage, tag, w.name.replace("^3", ""))
+    # whole step: the algorithmic bytes of one accepted step (rejected attempts are overhead)
+    # over the wall time per accepted step; and what the design moves, rejected attempts included
+    step_ms = wall * 1e3 / steps
+    design_bytes = sum(design[s - 1] * (prof[f"stage{s}"][1] if s > 1 else steps) for s in range(1, 7)) / steps * N
     out.update(
         value=N * steps / wall,
-        ms_per_step=wall * 1e3 / steps,
+        ms_per_step=step_ms,
         event_ms_per_step=ev_ms / steps,
         rejects=rejects,
         dt_last=diag[-1]["dt"],
@@ -103,14 +119,34 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
         xi_last=diag[-1]["xi"],
         E_first=diag[0]["E_M"],
         E_last=diag[-1]["E_M"],
-        fp64_final_xi=fin["xi"],
-        step_GBs=step_bytes * steps / wall / 1e9,
+        step_algorithmic_GBs=ALGO_STEP[tag] * N / (step_ms * 1e-3) / 1e9,
+        step_design_GBs=design_bytes / (step_ms * 1e-3) / 1e9,
         kernels=kernels,
-        roofline={"bound": "hbm", "kernel": f"stage_kernel<{dom[-1]}> ({tag})",
+        roofline={"bound": "hbm", "kernel": f"stage_kernel<{stage}> ({tag})",
                   "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                  "traffic": traffic, "algorithmic_bytes": bytes_node[int(dom[-1]) - 1] * N},
+                  "traffic": traffic, "algorithmic_bytes_per_node": algo[stage - 1],
+                  "algorithmic_bytes": algo[stage - 1] * N, "design_bytes_per_node": design[stage - 1],
+                  "design_GBs": kernels[dom]["design_GBs"]},
     )
     return out
+
+
+def mixed_vs_fp64_fixed(R, torch, w, dt, K):
+    """FP32-mixed against FP64 at identical t: both precisions take K steps of the same fixed
+    dt from x0; E_M of every step, and the FP64 diagnostics sweep of both final states."""
+    runs = {}
+    for prec in (R.RELAX_FP64, R.RELAX_FP32_MIXED):
+        cfg = R.make_config(w.grid, precision=prec, dt0=dt, adaptive=False)
+        with R.Relaxation(cfg, torch.from_numpy(w.x0).cuda(), torch.from_numpy(w.B0).cuda()) as r:
+            d = r.step(K)
+            runs[prec] = ([x["E_M"] for x in d], r.diagnostics())
+    (E64, f64), (E32, f32) = runs[R.RELAX_FP64], runs[R.RELAX_FP32_MIXED]
+
+    def rel(a, b):
+        return abs(a - b) / abs(b)
+    return {"steps": K, "dt": dt, "E_M_t_max_rel": max(rel(a, b) for a, b in zip(E32, E64)),
+            "final_E_M_rel": rel(f32["E_M"], f64["E_M"]), "final_xi_rel": rel(f32["xi"], f64["xi"]),
+            "final_R2_rel": rel(f32["R2"], f64["R2"]), "final_xi_fp64": f64["xi"], "final_R2_fp64": f64["R2"]}
 
 
 def measured_traffic(stage, tag, workload):
@@ -124,29 +160,35 @@ def measured_traffic(stage, tag, workload):
     return float(v) if v is not None else None
 
 
-def stream_bandwidth(torch, mib=1024, reps=5):
-    """What plain streaming kernels reach on this device, GB/s of bytes moved: a device-to-
-    device copy of `mib` MiB (the runtime's blit kernel, also the known-size kernel the HBM
-    byte counters are calibrated on), a read-only sum and a two-read one-write add."""
+def stream_bandwidth(R, torch, mib=1024, reps=10):
+    """GB/s (bytes moved) of the library's streaming reference kernel -- one FP64 element per
+    lane, non-temporal loads and stores, the sweeps' element width -- on arrays of `mib` MiB:
+    copy (1 read, 1 write), read only, 2 reads + 1 write, 4 reads + 1 write; plus torch's
+    device-to-device copy (the runtime's blit kernel, the known-size kernel the HBM byte
+    counters are calibrated on)."""
     n = mib * (1 << 20) // 8
-    a = torch.ones(n, dtype=torch.float64, device="cuda")
-    b = torch.ones(n, dtype=torch.float64, device="cuda")
-    c = torch.empty_like(a)
-
-    def rate(fn, nbytes):
-        fn()
-        torch.cuda.synchronize()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        start.record()
-        for _ in range(reps):
-            fn()
-        stop.record()
-        torch.cuda.synchronize()
-        return nbytes / (start.elapsed_time(stop) * 1e-3 / reps) / 1e9
-
-    out = {"copy": rate(lambda: c.copy_(a), 16 * n), "read": rate(lambda: a.sum(), 8 * n),
-           "add_2r1w": rate(lambda: torch.add(a, b, out=c), 24 * n)}
-    del a, b, c
+    src = torch.ones(4 * n, dtype=torch.float64, device="cuda")
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for kind, name, moved in ((0, "copy", 2), (1, "read", 1), (2, "add_2r1w", 3), (3, "sum_4r1w", 5)):
+        rc, ms = R.relax_stream_probe(kind, src.data_ptr(), dst.data_ptr(), n, reps, stream)
+        if rc != R.RELAX_OK:
+            raise R.RelaxError(rc, "relax_stream_probe")
+        out[name] = moved * 8 * n / (ms * 1e-3) / 1e9
+    a = src[:n]
+    dst.copy_(a)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        dst.copy_(a)
+    stop.record()
+    torch.cuda.synchronize()
+    out["torch_copy"] = 16 * n / (start.elapsed_time(stop) * 1e-3 / reps) / 1e9
+    del src, dst, a
+    # the best rate of a kernel that both reads and writes: what a sweep can hope for
+    out["read_write_ceiling"] = max(out["copy"], out["add_2r1w"], out["sum_4r1w"])
     return out
 
 
@@ -177,15 +219,57 @@ def adjoint_cost(R, torch, W, steps=200, every=20):
             "backward_ms_per_step": tb * 1e3 / steps, "backward_over_forward": tb / tf}
 
 
-def cpu_baseline(w, steps, dt):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_step_times(oracle, w, dt, steps):
+    """Wall seconds of each of `steps` fixed-dt oracle steps after one warm-up step, chained
+    from x0 (each call takes one step from the previous one's positions)."""
+    x = w.x0
+    times = []
+    for i in range(steps + 1):
+        t0 = time.perf_counter()
+        x = oracle.run(w.grid, x, w.B0, 1, dt=dt, mode=oracle.MODE_FIXED)["x"]
+        if i > 0:
+            times.append(time.perf_counter() - t0)
+    return times
+
+
+def cpu_baseline(W, w5, dt5, steps=5):
+    """The oracle as it stands (OpenMP, FP64) on this host: the median of `steps` fixed-dt
+    steps after one warm-up step, on the 256^3 benchmark box (the value) and on the 16^3 twist
+    and the 64x64x192 braid; all host threads, and one thread on the two smaller grids."""
+    import statistics
+
     import oracle
-    log(f"cpu baseline: oracle, {steps} fixed-dt steps on the full grid, {oracle.threads()} threads")
-    t0 = time.perf_counter()
-    oracle.run(w.grid, w.x0, w.B0, steps, dt=dt, mode=oracle.MODE_FIXED)
-    sec = time.perf_counter() - t0
-    return {"value": w.grid.N * steps / sec, "unit": "grid-point updates/s", "cores": oracle.threads(),
-            "kind": "oracle", "sample": f"{steps} fixed-dt Cash-Karp steps (dt {dt:.3g}) of the full "
-                                        f"{w.name} grid ({sec:.1f} s wall)"}
+    nthreads = oracle.threads()
+    res = {}
+    cases = [("abc_256^3", w5, dt5, [nthreads]), ("single_twist_16^3", W.single_twist_16(), 1e-3, [nthreads, 1]),
+             ("braid_64x64x192", W.braid(64, 192), 1e-2, [nthreads, 1])]
+    t_all = time.perf_counter()
+    for name, w, dt, thread_counts in cases:
+        for th in thread_counts:
+            oracle.set_threads(th)
+            log(f"cpu baseline: oracle on {name}, {th} thread(s), {steps} + 1 steps")
+            ts = _oracle_step_times(oracle, w, dt, steps)
+            med = statistics.median(ts)
+            res[f"{name}, {th} thread{'s' if th > 1 else ''}"] = {
+                "updates_per_s": w.grid.N / med, "median_step_s": med, "steps_timed": steps, "threads": th}
+    oracle.set_threads(nthreads)
+    main = res[f"abc_256^3, {nthreads} thread{'s' if nthreads > 1 else ''}"]
+    return {"value": main["updates_per_s"], "unit": "grid-point updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"median of {steps} fixed-dt Cash-Karp steps (dt {dt5:.3g}) of the full abc_256^3 grid "
+                      f"after one warm-up step; {os.cpu_count()} host CPUs ({_cpu_model()})",
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(), "by_config": res,
+            "total_s": time.perf_counter() - t_all}
 
 
 def main():
@@ -197,7 +281,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed", "both"], default="both")
     ap.add_argument("--tol", type=float, default=1e-7)
     ap.add_argument("--dt0", type=float, default=1e-3)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=5, help="timed oracle steps per configuration")
+    ap.add_argument("--accuracy-steps", type=int, default=20,
+                    help="fixed-dt steps of the FP32-mixed vs FP64 comparison at identical t")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost figure")
     args = ap.parse_args()
@@ -216,8 +302,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     R.lib()  # fail loudly if the HIP library is missing
-    stream = stream_bandwidth(torch)
-    copy_gbs = stream["copy"]
+    stream = stream_bandwidth(R, torch)
     log("device streaming GB/s: " + ", ".join(f"{k} {v:.0f}" for k, v in stream.items()))
     log(f"building inputs abc_{args.n}^3")
     w = W.abc_box(args.n)
@@ -228,6 +313,8 @@ def main():
         res["mixed"] = run_precision(R, torch, w, R.RELAX_FP32_MIXED, args.steps, args.warmup, args.tol, args.dt0)
     main_key = "fp64" if "fp64" in res else "mixed"
     m = res[main_key]
+    tag = "fp64" if main_key == "fp64" else "fp32-mixed"
+    ceiling = stream["read_write_ceiling"]
     line = {
         "metric": METRIC,
         "value": m["value"],
@@ -245,26 +332,33 @@ def main():
                                f"divergence-free |k|<=3 displacement (max 0.1, seed 5)",
                    "grid": list(w.grid.n), "step": "one accepted adaptive Cash-Karp RK5(4) step",
                    "tol": args.tol, "rejects_in_timed_steps": m["rejects"],
-                   "step_hbm_GBs_algorithmic": m["step_GBs"],
-                   "step_hbm_frac": m["step_GBs"] / HBM_PEAK_GBS},
+                   "step_algorithmic_bytes_per_node": ALGO_STEP[tag],
+                   "step_hbm_GBs_algorithmic": m["step_algorithmic_GBs"],
+                   "step_hbm_frac": m["step_algorithmic_GBs"] / HBM_PEAK_GBS,
+                   "step_frac_of_stream_ceiling": m["step_algorithmic_GBs"] / ceiling,
+                   "step_hbm_GBs_design": m["step_design_GBs"]},
         "roofline": m["roofline"],
         "kernels": m["kernels"],
-        "copy_GBs": copy_gbs,
         "stream_GBs": stream,
     }
     if main_key == "fp64" and "mixed" in res:
         mm = res["mixed"]
+        log(f"FP32-mixed vs FP64: {args.accuracy_steps} steps at the same fixed dt")
+        acc = mixed_vs_fp64_fixed(R, torch, w, dt=1e-4, K=args.accuracy_steps)
         line["fp32_mixed"] = {"value": mm["value"], "ms_per_step": mm["ms_per_step"], "dtype": "f64+f32",
                               "rejects_in_timed_steps": mm["rejects"], "roofline": mm["roofline"],
-                              "step_hbm_GBs_algorithmic": mm["step_GBs"], "kernels": mm["kernels"],
-                              "E_last_rel_diff_vs_fp64": abs(mm["E_last"] - m["E_last"]) / abs(m["E_last"])}
+                              "step_algorithmic_bytes_per_node": ALGO_STEP["fp32-mixed"],
+                              "step_hbm_GBs_algorithmic": mm["step_algorithmic_GBs"],
+                              "step_hbm_frac": mm["step_algorithmic_GBs"] / HBM_PEAK_GBS,
+                              "step_hbm_GBs_design": mm["step_design_GBs"], "kernels": mm["kernels"],
+                              "accuracy_vs_fp64_fixed_dt": acc}
     if not args.no_adjoint:
         log("adjoint cost: braid 64x64x192, 200 steps, checkpoints every 20")
         line["adjoint"] = adjoint_cost(R, torch, W)
     if not args.no_cpu_baseline:
-        # the oracle takes fixed steps of the size the adaptive GPU run settled to (dt0 itself
-        # is above the explicit stability limit of the 256^3 grid)
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps, dt=m["dt_last"])
+        # fixed steps of the size the adaptive GPU run settled to (dt0 itself is above the
+        # explicit stability limit of the 256^3 grid)
+        line["cpu_baseline"] = cpu_baseline(W, w, m["dt_last"], steps=args.cpu_steps)
     print(json.dumps(line), flush=True)
 
 

@@ -154,6 +154,17 @@ int relax_set_state(void* ctx, const double* d_x_in, double t, double dt);
  * NULL): index 0..5 = the six Runge-Kutta stage sweeps, 6 = the step-control kernel. */
 int relax_profile(void* ctx, int on, double* ms_out, long long* launches_out);
 
+/* Measurement aid, not part of the method: the bandwidth a plain streaming kernel with the
+ * stage sweeps' element width reaches (one FP64 element per lane, non-temporal loads and
+ * stores, grid-stride over n elements).  kind 0: out = in (copy, one read and one write per
+ * element); 1: read in only (out[0] is left as it is); 2: out = in[0:n] + in[n:2n] (two reads, one
+ * write); 3: out = the sum of four consecutive input arrays of n (four reads, one write).
+ * d_in holds n, n, 2n or 4n doubles and d_out n doubles (device).  Runs once untimed, then
+ * reps times; *ms_out (host) receives the mean duration of one run in milliseconds
+ * (HIP events on hip_stream).  Blocks until done. */
+int relax_stream_probe(int kind, const double* d_in, double* d_out, long long n, int reps, void* hip_stream,
+                       double* ms_out);
+
 /* Short English text of a status code (static storage). */
 const char* relax_strerror(int code);
 

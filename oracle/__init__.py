@@ -49,6 +49,8 @@ def lib():
     L.orc_rhs_sampled.restype = C.c_int
     L.orc_threads.argtypes = []
     L.orc_threads.restype = C.c_int
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = None
     L.orc_tableau.argtypes = [_dp, _dp, _dp]
     L.orc_tableau.restype = None
     for f in (L.orc_fields, L.orc_diagnostics, L.orc_ck_attempt, L.orc_controller, L.orc_run, L.orcz_run_fixed):
@@ -151,6 +153,11 @@ def ck_attempt(grid, x, B0, dt, gamma=1.0, want_k=False):
 def threads() -> int:
     """OpenMP threads the oracle's sweeps use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later sweeps (for timing it on a given core count)."""
+    lib().orc_set_threads(int(n))
 
 
 def tableau():

@@ -561,6 +561,11 @@ int orc_ck_attempt(const int n[3], const double h[3], const int bc[3], double ga
 /* OpenMP threads the sweeps use */
 int orc_threads(void) { return omp_get_max_threads(); }
 
+/* Set the OpenMP threads of later sweeps (timing of the oracle on a given core count). */
+void orc_set_threads(int n) {
+  if (n >= 1) omp_set_num_threads(n);
+}
+
 /* The Cash-Karp coefficients as stored: A (6x6, row s = stage), b5, b4. */
 void orc_tableau(double A[36], double b5[6], double b4[6]) {
   for (int s = 0; s < 6; s++) {

@@ -26,7 +26,9 @@ RELAX_FP64, RELAX_FP32_MIXED = 0, 1
 # every symbol include/relax.h declares
 EXPORTS = ("relax_workspace_bytes", "relax_init", "relax_step", "relax_diagnostics", "relax_velocity",
            "relax_fields", "relax_monitors", "relax_backward",
-           "relax_get_state", "relax_set_state", "relax_profile", "relax_strerror", "relax_last_error",
+           "relax_get_state", "relax_set_state", "relax_profile", "relax_stream_probe",
+           "relax_strerror",
+           "relax_last_error",
            "relax_destroy")
 
 
@@ -84,6 +86,8 @@ def lib():
     L.relax_set_state.argtypes = [vp, vp, C.c_double, C.c_double]
     L.relax_profile.argtypes = [vp, C.c_int, dp, C.POINTER(C.c_longlong)]
     L.relax_profile.restype = C.c_int
+    L.relax_stream_probe.argtypes = [C.c_int, vp, vp, C.c_longlong, C.c_int, vp, dp]
+    L.relax_stream_probe.restype = C.c_int
     L.relax_strerror.argtypes = [C.c_int]
     L.relax_strerror.restype = C.c_char_p
     L.relax_last_error.argtypes = [vp]
@@ -156,6 +160,14 @@ def relax_profile(ctx, on):
     n = (C.c_longlong * 7)()
     rc = lib().relax_profile(ctx, int(on), ms, n)
     return rc, list(ms), list(n)
+
+
+def relax_stream_probe(kind, d_in, d_out, n, reps, hip_stream):
+    """Streaming reference kernel (measurement aid); returns (rc, mean ms of one run)."""
+    ms = C.c_double(0.0)
+    rc = lib().relax_stream_probe(int(kind), C.c_void_p(d_in), C.c_void_p(d_out), int(n), int(reps),
+                                  C.c_void_p(hip_stream), C.byref(ms))
+    return rc, ms.value
 
 
 def relax_strerror(code: int) -> str:

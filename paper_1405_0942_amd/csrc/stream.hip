@@ -1,0 +1,92 @@
+// stream.hip -- streaming reference kernels: what a plain kernel with the stage sweeps'
+// element width (one 64-bit element per lane, wave64 rows of 512 contiguous bytes,
+// non-temporal loads and stores) reaches on this device.  A measurement aid for the
+// bandwidth ceiling that the sweeps are compared with; nothing on the relaxation path uses it.
+#include <hip/hip_runtime.h>
+
+#include "../../include/relax.h"
+
+namespace {
+
+constexpr int STREAM_THREADS = 256;
+constexpr int STREAM_UNROLL = 4;
+
+// out[i] = sum of the R inputs at i (R = 1: a copy); R inputs and one output of n doubles.
+// W = 0: read only (the sum of every element is folded into one value per lane, stored only
+// if it equals a value no input produces, so the loads cannot be removed).
+template <int R, int W>
+__global__ __launch_bounds__(STREAM_THREADS) void stream_kernel(const double* __restrict__ a0,
+                                                                const double* __restrict__ a1,
+                                                                const double* __restrict__ a2,
+                                                                const double* __restrict__ a3,
+                                                                double* __restrict__ out, long long n) {
+  const double* in[4] = {a0, a1, a2, a3};
+  const long long stride = (long long)gridDim.x * STREAM_THREADS * STREAM_UNROLL;
+  double acc = 0.0;
+  for (long long base = (long long)blockIdx.x * STREAM_THREADS * STREAM_UNROLL + threadIdx.x; base < n;
+       base += stride) {
+    double v[STREAM_UNROLL];
+#pragma unroll
+    for (int u = 0; u < STREAM_UNROLL; u++) v[u] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+#pragma unroll
+      for (int u = 0; u < STREAM_UNROLL; u++) {
+        const long long i = base + (long long)u * STREAM_THREADS;
+        if (i < n) v[u] += __builtin_nontemporal_load(in[r] + i);
+      }
+    }
+    if constexpr (W) {
+#pragma unroll
+      for (int u = 0; u < STREAM_UNROLL; u++) {
+        const long long i = base + (long long)u * STREAM_THREADS;
+        if (i < n) __builtin_nontemporal_store(v[u], out + i);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < STREAM_UNROLL; u++) acc += v[u];
+    }
+  }
+  if constexpr (!W) {
+    if (acc == -1.2345e300) out[0] = acc;
+  }
+}
+
+}  // namespace
+
+extern "C" int relax_stream_probe(int kind, const double* d_in, double* d_out, long long n, int reps,
+                                  void* hip_stream, double* ms_out) {
+  if (!d_in || !d_out || n <= 0 || reps < 1 || !ms_out || kind < 0 || kind > 3) return RELAX_E_ARG;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  // inputs: kind 0 and 1 read d_in[0, n); kinds 2 and 3 read 2 and 4 consecutive arrays of n
+  const double* a[4] = {d_in, d_in, d_in, d_in};
+  const int nin = kind == 2 ? 2 : (kind == 3 ? 4 : 1);
+  for (int r = 0; r < nin; r++) a[r] = d_in + (long long)r * n;
+  const int grid = 16384;
+  auto launch = [&]() {
+    switch (kind) {
+      case 0: hipLaunchKernelGGL((stream_kernel<1, 1>), dim3(grid), dim3(STREAM_THREADS), 0, st, a[0], a[1], a[2], a[3], d_out, n); break;
+      case 1: hipLaunchKernelGGL((stream_kernel<1, 0>), dim3(grid), dim3(STREAM_THREADS), 0, st, a[0], a[1], a[2], a[3], d_out, n); break;
+      case 2: hipLaunchKernelGGL((stream_kernel<2, 1>), dim3(grid), dim3(STREAM_THREADS), 0, st, a[0], a[1], a[2], a[3], d_out, n); break;
+      default: hipLaunchKernelGGL((stream_kernel<4, 1>), dim3(grid), dim3(STREAM_THREADS), 0, st, a[0], a[1], a[2], a[3], d_out, n); break;
+    }
+  };
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return RELAX_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return RELAX_E_HIP;
+  }
+  int rc = RELAX_OK;
+  launch();  // warm-up
+  float ms = 0.f;
+  if (hipEventRecord(e0, st) != hipSuccess) rc = RELAX_E_HIP;
+  for (int i = 0; i < reps && rc == RELAX_OK; i++) launch();
+  if (rc == RELAX_OK && (hipGetLastError() != hipSuccess || hipEventRecord(e1, st) != hipSuccess ||
+                         hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = RELAX_E_HIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms_out = ms / reps;
+  return rc;
+}

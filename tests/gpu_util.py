@@ -30,3 +30,14 @@ def context(grid, x0, B0, K_record=0, **cfg_kw):
 
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+def nrel_inc(x1, x0, xo1):
+    """Normwise relative error of the increment x1 - x0 against the oracle's xo1 - x0, up to the
+    rounding of the stored positions: a node may differ by one unit in the last place of its
+    stored coordinate (two sums that agree to a few ulps of the increment can still round the
+    position to neighbouring doubles), which is removed before the norm is taken."""
+    x1, x0, xo1 = (np.asarray(a, dtype=np.float64) for a in (x1, x0, xo1))
+    d = np.abs((x1 - x0) - (xo1 - x0))
+    ulp = np.spacing(np.maximum(np.abs(x1), np.abs(xo1)))
+    return float(np.maximum(d - ulp, 0.0).max() / max(np.abs(xo1 - x0).max(), 1e-300))

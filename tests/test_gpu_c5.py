@@ -1,0 +1,163 @@
+"""Full-step parity on the 256^3 periodic ABC box, in the launch configuration the benchmark
+times (x, y periodic specialisation, two z-chunks of 128 planes, periodic z wrap), FP64 and
+FP32-mixed, against the FP64 oracle; and node-wise FP32-mixed checks on a 64^3 ABC box, whose
+field has magnetic nulls on grid nodes.
+
+One fixed-dt Cash-Karp step (Sec. 2.4) from the same x0:
+
+* FP64: the increment x1 - x0 normwise within 1e-12 of the oracle's, up to one unit in the last
+  place of each stored position (at dt = 1e-4 the increment is about 1e-4 while the positions
+  reach 2 pi, so one ulp of a position, 8.9e-16, is 9e-12 of the increment: two correct sums
+  that round a node to neighbouring doubles differ by that much); the pre-step E_M within
+  1e-12, xi and R2 within 1e-11; the FP64 diagnostics sweep of the new positions against the
+  oracle's diagnostics of its own new positions (same bars).
+* FP32-mixed: E_M (pre-step, in-loop) and the FP64-evaluated E_M, xi and R2 of the new
+  positions within 1e-5 of the oracle; the increment normwise within INC_MIXED (below).
+
+The FP32-mixed increment bar.  Past the Jacobian the mixed sweep forms B, the differences
+G' = B(n + e_a) - B(n - e_a), c', J and J x B in FP32.  A difference of two FP32 values of
+size |B| carries an absolute error of about eps32 |B| = 6e-8 |B|, against a difference of
+size 2 h |grad B|; on these boxes (|grad B| ~ |B|, h = 2 pi / n) that is a relative error of
+eps32 / (2 h) ~ 1.2e-6 at 256^3 (3e-7 at 64^3), and the few further FP32 operations of c', J
+and the force multiply it by a small factor.  The increment dt sum b_s k_s inherits the
+normwise error of the k_s, so INC_MIXED = 2e-5 leaves about an order of magnitude over that
+estimate; the measured values are printed.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1405_0942_amd as R
+import workloads as W
+from gpu_util import banner, context, host, nrel, nrel_inc, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+DT = 1e-4          # below the explicit stability limit of the 256^3 box (the adaptive run settles near 1.05e-4)
+INC_MIXED = 2e-5   # normwise bar on the FP32-mixed increment (derivation in the module docstring)
+
+
+@pytest.fixture(scope="module")
+def abc256():
+    banner("abc 256^3: building inputs and the oracle's fixed step")
+    w = W.abc_box(256)
+    tau_B2 = oracle.null_threshold(w.B0)
+    o = oracle.run(w.grid, w.x0, w.B0, 1, dt=DT, mode=oracle.MODE_FIXED, tau_B2=tau_B2)
+    od1 = oracle.diagnostics(w.grid, o["x"], w.B0, tau_B2=tau_B2)
+    return w, tau_B2, o, od1
+
+
+def _gpu_step(w, precision):
+    with context(w.grid, w.x0, w.B0, dt0=DT, adaptive=False, precision=precision) as r:
+        d0 = r.step(1)[0]
+        x1 = host(r.state()[0])
+        d1 = r.diagnostics()
+    return d0, x1, d1
+
+
+def test_abc256_one_fixed_step_fp64(abc256):
+    w, tau_B2, o, od1 = abc256
+    banner("abc 256^3: one fixed FP64 step vs oracle")
+    d0, x1, d1 = _gpu_step(w, R.RELAX_FP64)
+    od = o["diag"][0]
+    e_raw = nrel(x1 - w.x0, o["x"] - w.x0)
+    e_inc = nrel_inc(x1, w.x0, o["x"])
+    banner(f"  increment {e_inc:.2e} beyond one ulp of x ({e_raw:.2e} raw); pre-step E_M {rel(d0['E_M'], od[2]):.1e} xi {rel(d0['xi'], od[3]):.1e} "
+           f"R2 {rel(d0['R2'], od[4]):.1e}; post-step E_M {rel(d1['E_M'], od1['E_M']):.1e} "
+           f"xi {rel(d1['xi'], od1['xi']):.1e} R2 {rel(d1['R2'], od1['R2']):.1e}")
+    assert e_inc < 1e-12
+    assert rel(d0["E_M"], od[2]) < 1e-12
+    assert rel(d0["xi"], od[3]) < 1e-11
+    assert rel(d0["R2"], od[4]) < 1e-11
+    assert rel(d0["min_det"], od[6]) < 1e-12
+    assert rel(d1["E_M"], od1["E_M"]) < 1e-12
+    assert rel(d1["xi"], od1["xi"]) < 1e-11
+    assert rel(d1["R2"], od1["R2"]) < 1e-11
+    assert rel(d1["min_det"], od1["min_det"]) < 1e-12
+
+
+def test_abc256_one_fixed_step_mixed(abc256):
+    w, tau_B2, o, od1 = abc256
+    banner("abc 256^3: one fixed FP32-mixed step vs the FP64 oracle")
+    d0, x1, d1 = _gpu_step(w, R.RELAX_FP32_MIXED)
+    od = o["diag"][0]
+    e_inc = nrel(x1 - w.x0, o["x"] - w.x0)
+    banner(f"  increment {e_inc:.2e} (bar {INC_MIXED:.0e}); pre-step E_M {rel(d0['E_M'], od[2]):.1e}; "
+           f"post-step (FP64 sweep) E_M {rel(d1['E_M'], od1['E_M']):.1e} xi {rel(d1['xi'], od1['xi']):.1e} "
+           f"R2 {rel(d1['R2'], od1['R2']):.1e}")
+    assert e_inc < INC_MIXED
+    assert rel(d0["E_M"], od[2]) < 1e-5
+    assert rel(d1["E_M"], od1["E_M"]) < 1e-5
+    assert rel(d1["xi"], od1["xi"]) < 1e-5
+    assert rel(d1["R2"], od1["R2"]) < 1e-5
+
+
+def test_abc64_mixed_nodewise_with_nulls():
+    """One fixed FP32-mixed step of the displaced 64^3 ABC box against the FP64 oracle, node by
+    node.  The field vanishes on grid nodes (every component is 0 at X = Y = Z = 3 pi / 4, node
+    24 at 64^3), where FP32 J x B has no correct digits relative to its own size; the error
+    there is still bounded by the FP32 rounding of B at the scale of the whole field, so each
+    node's increment error is compared with dt (|J||B|(n) + eps_loc max|J||B|): the local force
+    scale plus a floor at the field's scale."""
+    w = W.abc_box(64)
+    g = w.grid
+    dt = 1e-3
+    banner("abc 64^3: FP32-mixed step, node-wise vs oracle")
+    tau_B2 = oracle.null_threshold(w.B0)
+    f = oracle.fields(g, w.x0, w.B0)
+    B2 = (f["B"] ** 2).sum(0)
+    n_null = int((B2 < 1e-6 * B2.max()).sum())
+    assert n_null > 0, "the ABC box should hold near-null nodes"
+    o = oracle.run(g, w.x0, w.B0, 1, dt=dt, mode=oracle.MODE_FIXED, tau_B2=tau_B2)
+    with context(g, w.x0, w.B0, dt0=dt, adaptive=False, precision=R.RELAX_FP32_MIXED) as r:
+        r.step(1)
+        x1 = host(r.state()[0])
+    d_m, d_o = x1 - w.x0, o["x"] - w.x0
+    e_norm = nrel(d_m, d_o)
+    JB = np.sqrt((f["J"] ** 2).sum(0)) * np.sqrt(B2)
+    scale = dt * (JB + 1e-3 * JB.max())
+    e_node = np.abs(d_m - d_o).max(axis=0) / scale
+    worst = np.unravel_index(np.argmax(e_node), e_node.shape)
+    near = B2 < 1e-4 * B2.max()
+    banner(f"  normwise {e_norm:.2e}; node-wise max {e_node.max():.2e} at {worst} "
+           f"(|B|^2/max {B2[worst] / B2.max():.1e}); {n_null} near-null nodes, "
+           f"their worst {e_node[near].max():.2e}")
+    assert e_norm < INC_MIXED
+    assert e_node.max() < 1e-3
+    # the FP64-evaluated diagnostics of the new positions
+    d1 = oracle.diagnostics(g, x1, w.B0, tau_B2=tau_B2)
+    od1 = oracle.diagnostics(g, o["x"], w.B0, tau_B2=tau_B2)
+    assert rel(d1["E_M"], od1["E_M"]) < 1e-5
+    assert rel(d1["R2"], od1["R2"]) < 1e-5
+    assert rel(d1["xi"], od1["xi"]) < 1e-5
+
+
+def test_abc64_mixed_20_steps_vs_oracle():
+    """E_M of 20 fixed FP32-mixed steps and the FP64-evaluated final E_M, xi and R2 against the
+    FP64 oracle's trajectory."""
+    w = W.abc_box(64)
+    g = w.grid
+    dt, K = 1e-3, 20
+    banner(f"abc 64^3: {K} FP32-mixed steps vs oracle")
+    tau_B2 = oracle.null_threshold(w.B0)
+    o = oracle.run(g, w.x0, w.B0, K, dt=dt, mode=oracle.MODE_FIXED, tau_B2=tau_B2)
+    with context(g, w.x0, w.B0, dt0=dt, adaptive=False, precision=R.RELAX_FP32_MIXED) as r:
+        diag = r.step(K)
+        xK = host(r.state()[0])
+        fin = r.diagnostics()
+    E = np.array([d["E_M"] for d in diag])
+    errE = float(np.max(np.abs(E - o["diag"][:, 2]) / o["diag"][:, 2]))
+    of = oracle.diagnostics(g, o["x"], w.B0, tau_B2=tau_B2)
+    banner(f"  E_M(t) {errE:.1e}; final E_M {rel(fin['E_M'], of['E_M']):.1e} xi {rel(fin['xi'], of['xi']):.1e} "
+           f"R2 {rel(fin['R2'], of['R2']):.1e}; displacement {nrel(xK - w.x0, o['x'] - w.x0):.1e}")
+    assert errE < 1e-5
+    assert rel(fin["E_M"], of["E_M"]) < 1e-5
+    assert rel(fin["xi"], of["xi"]) < 1e-5
+    assert rel(fin["R2"], of["R2"]) < 1e-5
+    assert nrel(xK - w.x0, o["x"] - w.x0) < INC_MIXED

@@ -2,7 +2,7 @@
 against FP64 (128x128x384).
 
 * Braid 64x64x192, FP64, adaptive: the oracle replays the GPU's accepted dt sequence for
-  the first 300 steps (E_M, xi and the displacement compared step by step); the GPU then
+  the first 1000 steps (E_M, xi and the displacement compared step by step); the GPU then
   runs on to 4000 steps, and the oracle's diagnostics of the GPU's final positions must
   match the GPU's own FP64 diagnostics sweep of them.  (Run on, this discretization of the
   braid develops a grid-scale instability: xi bottoms out near 1.9e-2 around step 4250,
@@ -12,7 +12,9 @@ against FP64 (128x128x384).
 * Braid 128x128x384, FP64 and FP32-mixed, 5000 steps at the same fixed dt: E_M of every
   step and the final FP64-evaluated xi and R2 of the mixed run within 1e-5 relative of the
   FP64 run (the mixed mode keeps positions in FP64 and evaluates the final diagnostics with
-  the FP64 sweep); the first 10 mixed steps also against the oracle.
+  the FP64 sweep), and the final displacement x - X normwise within 1e-6 of the FP64 run's;
+  the first 100 mixed steps also against the oracle (E_M of every step within 1e-5, the
+  displacement after them within 1e-5).
 """
 import numpy as np
 import pytest
@@ -34,7 +36,7 @@ def test_braid_64_fp64_long_run_vs_oracle():
     w = W.braid(64, 192)
     g = w.grid
     tau_B2 = oracle.null_threshold(w.B0)
-    K_cmp, K_total = 300, 4000
+    K_cmp, K_total = 1000, 4000
     banner(f"braid 64x64x192 FP64 adaptive: {K_cmp} steps vs oracle replay, then to {K_total}")
     with context(g, w.x0, w.B0, dt0=w.dt0, tol=w.tol) as r:
         diag = r.step(K_cmp)
@@ -99,6 +101,9 @@ def test_braid_128_mixed_vs_fp64():
            f"R2 {rel(f32['R2'], f64['R2']):.2e}; displacement {nrel(x32 - w.x0, x64 - w.x0):.2e}; "
            f"in-loop xi FP64 {d64[-1]['xi']:.3e} mixed {d32[-1]['xi']:.3e}")
     assert errE < 1e-5
+    # FP32 stage vectors carry ~1e-6 relative error per evaluation; over the run the
+    # displacement of the mixed run stays within 1e-6 of the FP64 run's (measured 5e-8)
+    assert nrel(x32 - w.x0, x64 - w.x0) < 1e-6
     assert rel(f32["E_M"], f64["E_M"]) < 1e-5
     assert rel(f32["xi"], f64["xi"]) < 1e-5
     assert rel(f32["R2"], f64["R2"]) < 1e-5
@@ -108,8 +113,14 @@ def test_braid_128_mixed_vs_fp64():
     assert rel(f32["E_M"], o["E_M"]) < 1e-12
     assert rel(f32["R2"], o["R2"]) < 1e-11
     assert rel(f32["xi"], o["xi"]) < 1e-11
-    # the first mixed steps against the oracle
-    ref = oracle.run(g, w.x0, w.B0, 10, dt=dt, mode=oracle.MODE_FIXED, tau_B2=tau_B2)
-    errE10 = float(np.max(np.abs(E32[:10] - ref["diag"][:, 2]) / ref["diag"][:, 2]))
-    banner(f"  first 10 mixed steps vs oracle: E_M max rel {errE10:.2e}")
-    assert errE10 < 1e-5
+    # the first mixed steps against the oracle (a second mixed run, stopped after K_o steps)
+    K_o = 100
+    ref = oracle.run(g, w.x0, w.B0, K_o, dt=dt, mode=oracle.MODE_FIXED, tau_B2=tau_B2)
+    with context(g, w.x0, w.B0, dt0=dt, adaptive=False, precision=R.RELAX_FP32_MIXED) as r:
+        r.step(K_o, diag=False)
+        x_o = host(r.state()[0])
+    errEo = float(np.max(np.abs(E32[:K_o] - ref["diag"][:, 2]) / ref["diag"][:, 2]))
+    errxo = nrel(x_o - w.x0, ref["x"] - w.x0)
+    banner(f"  first {K_o} mixed steps vs oracle: E_M max rel {errEo:.2e}, displacement {errxo:.2e}")
+    assert errEo < 1e-5
+    assert errxo < 1e-5
