@@ -88,12 +88,15 @@ typedef struct {
                      0 in the per-step records of relax_step. */
 } relax_diag;
 
-/* Bytes of device workspace a context with this configuration needs.  K_record is the
+/* Bytes of device workspace a context with this configuration needs (the state of Sec. 1 and
+ * the Runge-Kutta stage vectors of Sec. 2.4, plus checkpoints for relax_backward).  K_record is the
  * number of steps relax_backward may later differentiate through (0 if record = 0).
  * Returns 0 for an invalid configuration. */
 size_t relax_workspace_bytes(const relax_config* cfg, int K_record);
 
-/* Create a context.  d_x0 (initial positions) and d_B0 (initial field at the nodes,
+/* Create a context (Sec. 1: the state is the map x(X, t) on the grid of reference positions X,
+ * with the field B0 = B(X, 0) frozen in through eq. "B transformation" of Sec. 2.1; boundary
+ * kinds of Sec. 2.5).  d_x0 (initial positions) and d_B0 (initial field at the nodes,
  * B(X, 0)) are [3][nz][ny][nx] FP64 device arrays; they are copied, so the caller may
  * free them afterwards.  d_workspace (>= relax_workspace_bytes(cfg, K_record) bytes,
  * 256-byte aligned) belongs to the context until relax_destroy.  A folded x0 returns
@@ -101,14 +104,18 @@ size_t relax_workspace_bytes(const relax_config* cfg, int K_record);
 int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const double* d_B0,
                void* d_workspace, size_t workspace_bytes, void* hip_stream, void** out_ctx);
 
-/* Advance by K accepted Cash-Karp steps (rejected attempts are redone inside).  If
+/* Advance by K accepted steps of the fifth-order adaptive Cash-Karp Runge-Kutta method with
+ * the step-size rule of Sec. 2.4 (eq. "time stepping"; fixed dt = dt0 if cfg->adaptive = 0)
+ * applied to dx/dt = u (Sec. 1, eqs. "x integration", "magneto friction").  Rejected attempts
+ * are redone inside.  If
  * host_diag is not NULL it receives K entries (host memory), one per accepted step.
  * On an error the steps completed before it are kept and reported in *steps_done (may be
  * NULL).  Blocks until the steps are done. */
 int relax_step(void* ctx, int K, relax_diag* host_diag, int* steps_done);
 
 /* FP64 diagnostics sweep of the current positions (also for a mixed-precision context):
- * fills t, dt (next step size), E_M, xi, R2, min_det and concave; Lambda and rejects are 0. */
+ * fills t, dt (next step size), E_M (Sec. 3.2.4, eq. "magnetic energy"), xi (Sec. 4.1), R2,
+ * min_det and concave (Sec. 3.2.3); Lambda and rejects are 0. */
 int relax_diagnostics(void* ctx, relax_diag* out);
 
 /* Velocity u = gamma J x B of the current positions (Sec. 1, eq. "magneto friction", with
@@ -134,18 +141,22 @@ int relax_fields(void* ctx, double* d_B_out, double* d_J_out);
  * is relax_diag.concave).  Either pointer may be NULL.  Blocks until done. */
 int relax_monitors(void* ctx, double* d_alpha_out, int* d_kappa_out);
 
-/* Reverse-mode gradient through the recorded fixed-dt trajectory (record = 1):
+/* Reverse-mode gradient (the transpose of the step of relax_step: Sec. 2.1 pull-back, Sec. 2.2
+ * mimetic current, Sec. 2.4 Runge-Kutta stages) through the recorded trajectory, with its dt
+ * sequence held fixed (record = 1):
  * d(seed_EM * E_M(x_K) + seed_R2 * R2(x_K)) / d(x0, B0), where x_K is the current state
  * and x0 the state at init / relax_set_state.  d_grad_x0, d_grad_B0: [3][nz][ny][nx] FP64
  * device arrays (overwritten).  Returns RELAX_E_STATE if nothing was recorded. */
 int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0, double* d_grad_B0);
 
-/* Copy the current positions to d_x_out (device, [3][nz][ny][nx] FP64) and read t and the
- * next step size; any output may be NULL. */
+/* Copy the current positions x(X, t) (Sec. 1, the Lagrangian map) to d_x_out (device,
+ * [3][nz][ny][nx] FP64) and read t and the next step size of the rule of Sec. 2.4; any output
+ * may be NULL. */
 int relax_get_state(void* ctx, double* d_x_out, double* t, double* dt);
 
-/* Replace the positions (device array, copied), t and dt; clears a failed state and the
- * recorded trajectory.  A folded state returns RELAX_E_FOLD. */
+/* Replace the positions x(X, t) (Sec. 1; device array, copied), t and dt; clears a failed
+ * state and the recorded trajectory.  A folded state (some det F <= 0, the breakdown of
+ * Sec. 4.4) returns RELAX_E_FOLD. */
 int relax_set_state(void* ctx, const double* d_x_in, double t, double dt);
 
 /* Per-kernel timing.  Returns the totals accumulated since the previous call (then resets

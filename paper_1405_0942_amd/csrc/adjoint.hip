@@ -36,80 +36,10 @@
 // transposed in-plane as soon as it is formed; buffer loads with masked-off lanes (offsets
 // past the record count) issued one plane step ahead, so no divergent branch surrounds a
 // memory instruction and the waits are exact.
-#include "relax_device.h"
+#include "sweep_common.h"
 
 namespace relax {
 namespace {
-
-__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
-// p mod 3 in [0, 3) for p >= -3072 (plane indices reach at most three planes below 0)
-__device__ __forceinline__ int mod3(int p) { return (int)((unsigned)(p + 3072) % 3u); }
-
-struct AxisIdx {
-  int i, w;
-  bool ok;
-};
-
-__device__ __forceinline__ AxisIdx resolve(int v, int n, int bc) {
-  AxisIdx r;
-  if (bc == BC_PERIODIC) {
-    r.w = floordiv(v, n);
-    r.i = v - r.w * n;
-    r.ok = true;
-  } else {
-    r.w = 0;
-    r.i = v;
-    r.ok = (v >= 0 && v < n);
-  }
-  return r;
-}
-
-// resolve() without divisions, exact for v in [-n, 2n): the plane indices of a z march lie
-// within three planes of [0, n) and n >= 4.  Other v give a wrong but in-range index.
-__device__ __forceinline__ AxisIdx resolve_near(int v, int n, int bc) {
-  if (bc == BC_PERIODIC) {
-    const int w = v < 0 ? -1 : (v >= n ? 1 : 0);
-    return AxisIdx{min(max(v - w * n, 0), n - 1), w, true};
-  }
-  return resolve(v, n, bc);
-}
-
-// element index of a masked-off lane (scaled by 8 it lies past every plane's record count)
-constexpr unsigned IE = 1u << 28;
-constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer resource, gfx9 encoding
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base, unsigned nxy) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)(nxy * 8u), RSRC_WORD3);
-}
-// CP: cache policy; 2 (nt, non-temporal) on the single-use node-wise accesses, so that they
-// do not push the stencilled halo lines out of L2
-template <int CP = 0>
-__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, unsigned e) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, CP));
-}
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned e, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, 2);
-}
-
-__device__ __forceinline__ int logical_block(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int xcd = bid & 7, j = bid >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + j;
-}
-
-__device__ __forceinline__ double det3(const double F[3][3]) {
-  return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-         F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-}
-
-__device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
 
 __device__ __forceinline__ void cross(const double a[3], const double b[3], double o[3]) {
   o[0] = a[1] * b[2] - a[2] * b[1];
@@ -219,14 +149,14 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     for (int m = 0; m < 3; m++) {
       const auto rs = plane_rsrc(wsrc + m * N + zo, nxy);
 #pragma unroll
-      for (int r = 0; r < NP2; r++) wx[r][m] = bload(rs, w2e[r]);
+      for (int r = 0; r < NP2; r++) wx[r][m] = bload<double>(rs, w2e[r]);
     }
     if constexpr (WK) {
 #pragma unroll
       for (int m = 0; m < 3; m++) {
         const auto rs = plane_rsrc(k1p + m * N + zo, nxy);
 #pragma unroll
-        for (int r = 0; r < NP2; r++) wk[r][m] = bload(rs, w2e[r]);
+        for (int r = 0; r < NP2; r++) wk[r][m] = bload<double>(rs, w2e[r]);
       }
     }
   };
@@ -262,8 +192,8 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       const auto rv = plane_rsrc(vsrc + m * N + zo, nxy);
 #pragma unroll
       for (int r = 0; r < NP1; r++) {
-        b0r[r][m] = bload(rb, f1e[r]);
-        vr[r][m] = bload(rv, v_on ? f1e[r] : IE);
+        b0r[r][m] = bload<double>(rb, f1e[r]);
+        vr[r][m] = bload<double>(rv, v_on ? f1e[r] : IE);
       }
     }
   };
@@ -271,7 +201,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     const bool on = (pz >= z0 && pz < z1);
     const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
-    for (int m = 0; m < 3; m++) bbr[m] = bload<2>(plane_rsrc(a.B0bar + m * N + zo, nxy), on ? out_e : IE);
+    for (int m = 0; m < 3; m++) bbr[m] = bload<double, CPOL_STREAM>(plane_rsrc(a.B0bar + m * N + zo, nxy), on ? out_e : IE);
   };
   double so_F[9], so_B[3];
 #pragma unroll

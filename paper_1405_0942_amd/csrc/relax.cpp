@@ -26,7 +26,7 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 struct Layout {
-  size_t ctl, x0, x1, k[5], y[2], acc, B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
+  size_t ctl, x0, x1, k[3], y3, d4, y5, sum[3], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
   // reverse mode (record = 1): segment positions and stage vectors, cotangents, seed
   size_t ctl2, seg_x, seg_k, seg_y, Fbar, xbar, ybar, ubar, B0bar, useed;
   int ckpt_slots;
@@ -42,9 +42,11 @@ struct Ctx {
   Layout L{};
   Control* d_ctl = nullptr;
   double* d_x[2] = {nullptr, nullptr};
-  void* d_k[5] = {};
-  double* d_acc[3] = {nullptr, nullptr, nullptr};
-  double* d_y[2] = {nullptr, nullptr};
+  void* d_k[3] = {};
+  void* d_sum[3] = {};
+  void* d_d4 = nullptr;
+  double* d_y3 = nullptr;
+  double* d_y5 = nullptr;
   void* d_B0 = nullptr;
   double* d_B0_64 = nullptr;
   double* d_part = nullptr;
@@ -172,11 +174,13 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   L.ctl = take(sizeof(Control));
   L.x0 = take(N3 * sizeof(double));
   L.x1 = take(N3 * sizeof(double));
-  // FP64: k_1..k_3 and the partial sums of stage 4; FP32-mixed: k_1..k_5 (see stage.hip)
-  const bool mixed = (c->precision == RELAX_FP32_MIXED);
-  for (int s = 0; s < 5; s++) L.k[s] = (s < 3 || mixed) ? take(N3 * ts) : 0;
-  for (int t = 0; t < 2; t++) L.y[t] = take(N3 * sizeof(double));
-  L.acc = mixed ? 0 : take(3 * N3 * sizeof(double));
+  // k_1..k_3, the stage inputs y_3 and y_5 (FP64), the stage-4 increment d_4 and the partial
+  // sums P6, X, E (stage.hip)
+  for (int s = 0; s < 3; s++) L.k[s] = take(N3 * ts);
+  L.y3 = take(N3 * sizeof(double));
+  L.d4 = take(N3 * ts);
+  L.y5 = take(N3 * sizeof(double));
+  for (int i = 0; i < 3; i++) L.sum[i] = take(N3 * ts);
   L.B0_64 = take(N3 * sizeof(double));
   L.B0 = (c->precision == RELAX_FP32_MIXED) ? take(N3 * sizeof(float)) : L.B0_64;
   L.part = take((size_t)g.nblocks * NPART * sizeof(double));
@@ -226,10 +230,12 @@ SweepArgs sweep_args(Ctx* c) {
   a.x[1] = c->d_x[1];
   a.xout[0] = c->d_x[0];
   a.xout[1] = c->d_x[1];
-  for (int s = 0; s < 5; s++) a.k[s] = c->d_k[s];
-  for (int i = 0; i < 3; i++) a.acc[i] = c->d_acc[i];
-  a.k[5] = nullptr;
-  for (int t = 0; t < 4; t++) a.y[t] = c->d_y[(t + 1) & 1];  // y_3 .. y_6 alternate between two buffers
+  for (int s = 0; s < 3; s++) a.k[s] = c->d_k[s];
+  a.y3 = c->d_y3;
+  a.d4 = c->d_d4;
+  a.y5 = c->d_y5;
+  for (int i = 0; i < 3; i++) a.sum[i] = c->d_sum[i];
+  a.yrec[0] = a.yrec[1] = nullptr;
   a.B0 = c->d_B0;
   a.ctl = c->d_ctl;
   a.part = c->d_part;
@@ -347,10 +353,11 @@ int relax_init(const relax_config* cfg, int K_record, const double* d_x0, const 
   c->d_ctl = reinterpret_cast<Control*>(c->base + L.ctl);
   c->d_x[0] = reinterpret_cast<double*>(c->base + L.x0);
   c->d_x[1] = reinterpret_cast<double*>(c->base + L.x1);
-  for (int s = 0; s < 5; s++) c->d_k[s] = (s < 3 || c->mixed) ? c->base + L.k[s] : nullptr;
-  if (!c->mixed)
-    for (int i = 0; i < 3; i++) c->d_acc[i] = reinterpret_cast<double*>(c->base + L.acc) + (size_t)i * 3 * c->g.N;
-  for (int t = 0; t < 2; t++) c->d_y[t] = reinterpret_cast<double*>(c->base + L.y[t]);
+  for (int s = 0; s < 3; s++) c->d_k[s] = c->base + L.k[s];
+  c->d_y3 = reinterpret_cast<double*>(c->base + L.y3);
+  c->d_d4 = c->base + L.d4;
+  c->d_y5 = reinterpret_cast<double*>(c->base + L.y5);
+  for (int i = 0; i < 3; i++) c->d_sum[i] = c->base + L.sum[i];
   c->d_B0_64 = reinterpret_cast<double*>(c->base + L.B0_64);
   c->d_B0 = c->base + L.B0;
   c->d_part = reinterpret_cast<double*>(c->base + L.part);
@@ -583,7 +590,7 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
     const int len = (int)(s1 - s0);
     HIP_TRY(c, hipMemcpyAsync(c->d_seg_x, c->d_ckpt + (size_t)seg * N3, N3 * sizeof(double),
                               hipMemcpyDeviceToDevice, st));
-    // forward recompute, keeping x_n, k_1..k_5 and y_3..y_6 of every step
+    // forward recompute, keeping x_n, k_1..k_3 and y_3..y_6 of every step
     for (int j = 0; j < len; j++) {
       HIP_TRY(c, launch_seg_step(c->d_ctl2, c->d_dtrec, s0 + j, st));
       fw.x[0] = c->d_seg_x + (size_t)j * N3;
@@ -591,8 +598,13 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
       fw.xout[0] = c->d_seg_x + (size_t)j * N3;
       fw.xout[1] = c->d_seg_x + (size_t)(j + 1) * N3;
       for (int s = 0; s < 3; s++) fw.k[s] = c->d_seg_k + ((size_t)j * 3 + s) * N3;
-      for (int t = 0; t < 4; t++) fw.y[t] = c->d_seg_y + ((size_t)j * 4 + t) * N3;
-      for (int s = 1; s <= 6; s++) HIP_TRY(c, launch_stage(s, false, fw, st));
+      // y_3 .. y_6 of step j: stages 2 and 4 write y_3 and y_5 there; stages 4 and 6 add y_4, y_6
+      double* ys = c->d_seg_y + (size_t)j * 4 * N3;
+      fw.y3 = ys;
+      fw.yrec[0] = ys + N3;
+      fw.y5 = ys + 2 * N3;
+      fw.yrec[1] = ys + 3 * N3;
+      for (int s = 1; s <= 6; s++) HIP_TRY(c, launch_stage_rec(s, fw, st));
     }
     for (int j = len - 1; j >= 0; j--) {
       a.x = c->d_seg_x + (size_t)j * N3;

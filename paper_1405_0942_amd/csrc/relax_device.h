@@ -65,9 +65,12 @@ struct SweepArgs {
   Geometry g;
   const double* x[2];  // position buffers (x_n is x[ctl->cur])
   double* xout[2];     // same buffers, writable (stage 6 writes x[1 - cur])
-  void* k[6];          // stage vectors k1..k5 (double, or float in mixed mode)
-  double* y[4];        // stage inputs y_3..y_6 (y_t in y[t - 3]), written by stages 2..5
-  double* acc[3];      // FP64 mode: partial sums Y6, dX, E written by stage 4 (see stage.hip)
+  void* k[3];          // stage vectors k_1..k_3 (double, or float in mixed mode)
+  double* y3;          // stage input y_3, written by stage 2
+  void* d4;            // stage-4 increment d_4 (element type of k), written by stage 3
+  double* y5;          // stage input y_5, written by stage 4
+  void* sum[3];        // partial sums P6 (d_6 after stage 5), X, E (element type of k; see stage.hip)
+  double* yrec[2];     // forward replay of the reverse pass: y_4 and y_6 at the node
   const void* B0;      // initial field (double, or float in mixed mode)
   Control* ctl;
   double* part;        // [nblocks][NPART] reduction partials of stage 1 / diagnostics
@@ -123,6 +126,9 @@ struct CK {
 // ------------------------------------------------------------------------------------------
 // stage s in 1..6; mixed selects float k / B0 storage
 hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st);
+// FP64 stage s of the forward replay of the reverse pass: stages 4 and 6 also store their
+// stage input at the node into a.yrec
+hipError_t launch_stage_rec(int s, const SweepArgs& a, hipStream_t st);
 hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st);  // FP64 sweep of x[diag_buf]
 hipError_t launch_control(Control* ctl, const double* part, const double* lam_part, int nblocks,
                           double* ring, double* dt_record, hipStream_t st);

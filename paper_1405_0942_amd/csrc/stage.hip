@@ -3,8 +3,8 @@
 // One launch evaluates, for every node, the right-hand side u = gamma J x B of the
 // Lagrangian relaxation (eq. "magneto friction") at the stage input
 //     y_s = x_n + dt sum_{j<s} a_sj k_j                  (Cash-Karp RK5(4), Sec. 2.4)
-// and stores k_s = u(y_s).  Stage 1 also reduces the diagnostics of x_n (E_M with the
-// face weights zeta, eq. "magnetic energy"; xi = max |J x B| / B^2; R2; min Delta);
+// and stores what the later stages need.  Stage 1 also reduces the diagnostics of x_n (E_M
+// with the face weights zeta, eq. "magnetic energy"; xi = max |J x B| / B^2; R2; min Delta);
 // stage 6 writes x_{n+1} with the fifth-order weights and reduces the embedded error
 // Lambda = max |x5 - x4|.
 //
@@ -24,12 +24,27 @@
 // paper's 3x3 system is (cof F)^T J = c, solved by J = F c / det F; with F = F' diag(1/2h)
 // and G = G' diag(1/2h) every spacing factor cancels.
 //
-// Stage inputs.  Stage 1 differentiates x_n; stage 2 assembles y_2 = x_n + dt a_21 k_1
-// from x_n and k_1 on the fly.  Stages 2..5 also write the NEXT stage's input pointwise,
-//     y_{s+1} = y_s + dt sum_{j<s} (a_{s+1,j} - a_{s,j}) k_j + dt a_{s+1,s} k_s,
-// so stages 3..6 stencil one vector (y_s) instead of x_n and every earlier k_j with
-// halos; the k_j they still need are read at the output node only.  A retried step
-// (smaller dt, same x_n and k_1) starts again at stage 2, which rebuilds y_2 and y_3.
+// Stage inputs.  Every stage input is x_n plus ONE rounded increment, y_s = x_n + d_s with
+// d_s = dt sum_j a_sj k_j summed first: the stencil differentiates y_s twice, and on a fine
+// grid a rounding of y_s is amplified by about 1/h^2 in u, so the inputs are rounded once from
+// x_n (as the plain definition does) and never accumulated stage by stage.  A stencilled
+// window holds at most two vectors (more overflow each XCD's L2 with halo lines); what a
+// stage needs at its output node from its own window (x_n, and k_1 in stage 2) is carried in
+// registers from the window load, three plane steps earlier, instead of being read again.
+//   stage 1: window x_n                    -> k_1
+//   stage 2: window x_n + dt a_21 k_1      -> k_2, y_3 = x_n + dt (a_31 k_1 + a_32 k_2)
+//   stage 3: window y_3; k_1, k_2 at node  -> k_3, d_4 = dt (a_41 k_1 + a_42 k_2 + a_43 k_3)
+//   stage 4: window x_n + d_4; k_1..k_3    -> y_5 = x_n + d_5 and the partial sums of k_1..k_4
+//            P6 = dt sum a_6j k_j, X = dt sum b5_j k_j, E = dt sum (b5_j - b4_j) k_j
+//   stage 5: window y_5; P6, E at node     -> P6 += dt a_65 k_5 (now d_6), E += dt (b5_5 - b4_5) k_5
+//   stage 6: window x_n + d_6; X, E        -> x_{n+1} = x_n + (X + dt b5_6 k_6),
+//                                             Lambda = max |E + dt (b5_6 - b4_6) k_6|
+// k_4, k_5 and k_6 are never stored.  HBM bytes per node and attempt: 864 (FP64), 540
+// (FP32-mixed: the k_j, d_4 and the partial sums in FP32; x_n, y_3 and y_5 in FP64).  x_{n+1}
+// is x_n plus an increment built from the k_j alone, so the step keeps full relative precision
+// however small it is.  A retried step (smaller dt, same x_n and k_1) starts again at stage 2,
+// and every stored vector is rewritten before it is read again.  REC (the forward replay of
+// the reverse pass) also stores y_4 and y_6 at the node for the reverse sweeps.
 //
 // Data flow: a workgroup owns a 64 x 8 (x, y) tile and marches up a z-chunk.  Each plane
 // of the stage input (tile + 2-node halo, FP64) goes into an LDS ring of three planes;
@@ -42,100 +57,10 @@
 // before its use, in the same order on every step, and waited for by exact counts.
 #include <type_traits>
 
-#include "relax_device.h"
+#include "sweep_common.h"
 
 namespace relax {
 namespace {
-
-__device__ __forceinline__ int floordiv(int a, int n) { return a >= 0 ? a / n : -((-a + n - 1) / n); }
-// p mod 3 in [0, 3) for p >= -3072 (plane indices reach at most three planes below 0)
-__device__ __forceinline__ int mod3(int p) { return (int)((unsigned)(p + 3072) % 3u); }
-
-struct AxisIdx {
-  int i;   // in-range index
-  int w;   // periods wrapped
-  bool ok;
-};
-
-__device__ __forceinline__ AxisIdx resolve(int v, int n, int bc) {
-  AxisIdx r;
-  if (bc == BC_PERIODIC) {
-    r.w = floordiv(v, n);
-    r.i = v - r.w * n;
-    r.ok = true;
-  } else {
-    r.w = 0;
-    r.i = v;
-    r.ok = (v >= 0 && v < n);
-  }
-  return r;
-}
-
-// resolve() without divisions, exact for v in [-n, 2n): the plane indices of a z march lie
-// within three planes of [0, n) and n >= 4.  Other v give a wrong but in-range index.
-__device__ __forceinline__ AxisIdx resolve_near(int v, int n, int bc) {
-  if (bc == BC_PERIODIC) {
-    const int w = v < 0 ? -1 : (v >= n ? 1 : 0);
-    return AxisIdx{min(max(v - w * n, 0), n - 1), w, true};
-  }
-  return resolve(v, n, bc);
-}
-
-// ---- buffer access --------------------------------------------------------------------------
-// Element index of a masked-off lane: scaled by the element size it lands at or past the
-// record count of every plane (a plane holds fewer than 2^28 nodes).
-constexpr unsigned IE = 1u << 28;
-constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer resource, gfx9 encoding
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-
-// resource for one component plane [base, base + nxy)
-template <typename V>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const V* base, unsigned nxy) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<V*>(base), 0, (int)(nxy * sizeof(V)), RSRC_WORD3);
-}
-// cache policy of the single-use accesses (node-wise loads and all stores); the stencilled
-// loads keep the default so that neighbouring tiles find their halo lines in L2
-#ifndef RELAX_STREAM_CPOL
-#define RELAX_STREAM_CPOL 2  // nt: non-temporal
-#endif
-template <typename V, int CP = 0>
-__device__ __forceinline__ V bload(__amdgpu_buffer_rsrc_t r, unsigned e) {
-  if constexpr (sizeof(V) == 8)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(e * 8u), 0, CP));
-  else
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(e * 4u), 0, CP));
-}
-template <typename V>
-__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, unsigned e, V v) {
-  if constexpr (sizeof(V) == 8)
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)(e * 8u), 0, RELAX_STREAM_CPOL);
-  else
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(e * 4u), 0, RELAX_STREAM_CPOL);
-}
-
-// logical tile of this workgroup; consecutive logical tiles share an XCD (the hardware
-// hands workgroup b to XCD b mod 8), so neighbouring tiles reuse each other's halos in L2
-__device__ __forceinline__ int logical_block(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int xcd = bid & 7, j = bid >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + j;
-}
-
-template <typename T>
-__device__ __forceinline__ T det3(const T F[3][3]) {
-  return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
-         F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-}
-
-// 1/d by the hardware estimate and two Newton steps (d is a positive normal number here;
-// d <= 0 means a folded cell, which the step control reports from det F itself)
-__device__ __forceinline__ double rcp_nr(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -156,42 +81,33 @@ __device__ __forceinline__ double wave_min(double v) {
   return v;
 }
 
-// the k_j a stage reads at its output node: k_1..k_{s-1} for stages 2..5 (for y_{s+1});
-// k_1, k_3, k_4, k_5 for stage 6 (the weights of k_2 in x5 and in x5 - x4 vanish).  With
-// FP64 stage vectors, stage 4 instead writes the three sums the last two stages need
-// (see PART below), and stages 5 and 6 read those.
-template <int S>
-__device__ __forceinline__ constexpr int point_k(int j) {
-  return (S == 6) ? (j == 0 ? 0 : j + 1) : j;
-}
-
-// S: stage 1..6.  MIXED: k and B0 in FP32 and the stencil past F' in FP32.  XYP: x and y
-// both periodic (no line-tied rows in x and y).  DIAG (stage 1, FP64): the diagnostics sweep
-// of x[diag_buf]: no step gating and no k_1; writes u (optionally scaled by det F), B and J
-// where the caller asked for them.
-template <int S, bool MIXED, bool XYP, bool DIAG = false>
+// S: stage 1..6.  MIXED: the k_j, the partial sums and B0 in FP32, and the stencil past F' in
+// FP32.  XYP: x and y both periodic (no line-tied rows in x and y).  DIAG (stage 1, FP64): the
+// diagnostics sweep of x[diag_buf]: no step gating and no k_1; writes u (optionally scaled by
+// det F), B, J, alpha* and the convexity where the caller asked for them.  REC (FP64 stages
+// 4 and 6): also store the stage input at the node, for the reverse sweeps.
+template <int S, bool MIXED, bool XYP, bool DIAG = false, bool REC = false>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(SweepArgs a) {
   using T = typename std::conditional<MIXED, float, double>::type;
   constexpr bool STAGE1 = (S == 1);
   constexpr bool LAST = (S == 6);
-  constexpr bool WK = (S == 2);                                // the window carries k_1 too
-  // PART (FP64): stage 4 writes, besides y_5,
-  //   Y6 = x_n + dt sum_{j<=4} a_6j k_j   (from y_4: a stage input, rounded like y_4),
-  //   dX = dt sum_{j<=4} b5_j k_j,  E = dt sum_{j<=4} (b5_j - b4_j) k_j   (from the k_j only);
-  // stage 5 forms y_6 = Y6 + dt a_65 k_5 and adds its term to E in place; stage 6 forms
-  // x_{n+1} = x_n + (dX + dt b5_6 k_6) -- x_n plus an increment made of k_j alone, so the
-  // step keeps full relative precision however small it is -- and the error E + dt (b5_6 -
-  // b4_6) k_6.  k_4 and k_5 are never stored.  (With FP32 stage vectors the FP64 sums would
-  // move more bytes than the k_j they replace, so the mixed mode keeps k_4 and k_5.)
-  constexpr bool PART = !MIXED;
-  constexpr bool PART_IN = PART && (S == 5 || S == 6);        // reads two sums, no k_j
-  constexpr int NPK = (STAGE1 || PART_IN) ? 0 : (LAST ? 4 : S - 1);  // k_j read at the output node
+  // the window is a base vector (x_n; y_3 in stage 3, y_5 in stage 5) plus at most one vector
+  // v with coefficient cv: k_1 (cv = dt a_21) in stage 2, d_4 and d_6 (cv = 1) in stages 4, 6
+  constexpr bool WV = (S == 2 || S == 4 || LAST);
+  // own-node values carried from the window to the output node (3 planes later): x_n in
+  // stages 2, 4, 6 (and k_1 in stage 2)
+  constexpr bool CX = WV;
+  constexpr bool CK1 = (S == 2);
+  constexpr int NPK = (S == 3) ? 2 : (S == 4 ? 3 : 0);  // k_j read at the output node
   constexpr int NPKA = NPK > 0 ? NPK : 1;
+  constexpr bool PS = (S == 5 || LAST);  // two partial sums read at the output node
+  constexpr bool SUMS_OUT = (S == 3 || S == 4 || S == 5);
   constexpr int NP2 = (RY2 * RX2 + NTHREADS - 1) / NTHREADS;  // stage-input points per thread
   constexpr int NP1 = (RY1 * RX1 + NTHREADS - 1) / NTHREADS;  // field points per thread
+  static_assert(!DIAG || (S == 1 && !MIXED), "the diagnostics sweep is the FP64 stage-1 sweep");
+  static_assert(!REC || (!MIXED && (S == 4 || S == 6)), "REC: FP64 stages 4 and 6");
 
   Control* ctl = a.ctl;
-  static_assert(!DIAG || (S == 1 && !MIXED), "the diagnostics sweep is the FP64 stage-1 sweep");
   constexpr bool diag_only = DIAG;
   int cur;
   double dt = 0.0;
@@ -214,29 +130,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   }
   const double gamma = ctl->gamma;
   const double tau_B2 = ctl->tau_B2;
-  // y_2 = x + c21 k_1 (stage-2 window); y_{s+1} = y_s + sum_j cy[j] k_j + cys k_s (output)
-  const double c21 = dt * CK::a[1][0];
-  double cy[NPKA] = {};
-  double cys = 0.0;
-  if constexpr (S >= 2 && S <= 5) {
-#pragma unroll
-    for (int j = 0; j < NPK; j++) cy[j] = dt * (CK::a[S][j] - CK::a[S - 1][j]);
-    cys = dt * CK::a[S][S - 1];
-  }
-  // PART, stage 4: Y6 from y_4, dX and E from the k_j (cp[0..2][j] for k_1..k_3, cps[0..2]
-  // for k_4)
-  double cp[3][PART && S == 4 ? 3 : 1] = {}, cps[3] = {0.0, 0.0, 0.0};
-  if constexpr (PART && S == 4) {
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-      cp[0][j] = dt * (CK::a[5][j] - CK::a[3][j]);
-      cp[1][j] = dt * CK::b5[j];
-      cp[2][j] = dt * (CK::b5[j] - CK::b4[j]);
-    }
-    cps[0] = dt * CK::a[5][3];
-    cps[1] = dt * CK::b5[3];
-    cps[2] = dt * (CK::b5[3] - CK::b4[3]);
-  }
+  const double cv = (S == 2) ? dt * CK::a[1][0] : 1.0;
 
   const Geometry& g = a.g;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
@@ -263,8 +157,8 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   __shared__ double red[NTHREADS / 64][NPART];
 
   const double* __restrict__ xn = a.x[cur];
-  const double* __restrict__ wsrc = (S <= 2) ? xn : a.y[S > 2 ? S - 3 : 0];  // the stencilled vector
-  const T* __restrict__ k1p = static_cast<const T*>(a.k[0]);
+  const double* __restrict__ wbase = (S == 3) ? a.y3 : ((S == 5) ? a.y5 : xn);  // the window base
+  const T* __restrict__ wvec = static_cast<const T*>(S == 2 ? a.k[0] : (S == 4 ? a.d4 : a.sum[0]));
   const T* __restrict__ b0p = static_cast<const T*>(a.B0);
 
   // plane index of a load (line-tied z: clamped; such planes are loaded but never used)
@@ -273,17 +167,41 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     return min(max(pz, 0), nz - 1);
   };
 
-  // ---- per-thread index tables: the (x, y) part of every address is the same on all planes
+  // ---- per-thread index tables: the (x, y) part of every address is the same on all planes.
+  // Window point e, row-major over the window; in the stages that carry own-node values,
+  // e < NTHREADS is the tile node of thread e instead (each thread loads its own node), then
+  // the two rows below and the two above the tile, then the two columns on either side.
   unsigned w2e[NP2];  // stage-input window point -> flat (x, y) index, IE off the grid
   int w2w[NP2];       // its periodic wraps: x in the low 16 bits, y in the high 16 bits (signed)
+  int w2o[NP2];       // its LDS offset, -1 past the window
 #pragma unroll
   for (int r = 0; r < NP2; r++) {
     const int e = tid + r * NTHREADS;
-    const int row = e / RX2, col = e - row * RX2;
+    int row, col;
+    if (!CX) {
+      row = e / RX2;
+      col = e - row * RX2;
+    } else if (e < NTHREADS) {
+      row = e / TX + 2;
+      col = e % TX + 2;
+    } else {
+      const int e2 = e - NTHREADS;
+      if (e2 < 4 * RX2) {
+        const int band = e2 / RX2;
+        row = band < 2 ? band : RY2 - 4 + band;
+        col = e2 - band * RX2;
+      } else {
+        const int e3 = e2 - 4 * RX2, side = e3 & 3;
+        row = 2 + (e3 >> 2);
+        col = side < 2 ? side : RX2 - 4 + side;
+      }
+    }
+    const bool in_win = e < RY2 * RX2;
     const AxisIdx rx = resolve(i0 + col - 2, nx, bcx);
     const AxisIdx ry = resolve(j0 + row - 2, ny, bcy);
-    w2e[r] = (e < RY2 * RX2 && rx.ok && ry.ok) ? (unsigned)(ry.i * nx + rx.i) : IE;
+    w2e[r] = (in_win && rx.ok && ry.ok) ? (unsigned)(ry.i * nx + rx.i) : IE;
     w2w[r] = (ry.w << 16) + (rx.w & 0xffff);
+    w2o[r] = in_win ? row * RX2 + col : -1;
   }
   // field point e: e < NTHREADS is the tile node of thread e; the rest is the halo ring
   unsigned f1e[NP1];
@@ -323,50 +241,70 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                                 (bcy == BC_LINE_TIED && (gj_t == 0 || gj_t == ny - 1)));
 
   // ---- loads of one plane, issued one plane step ahead of their use -------------------------
-  double wx[NP2][3];       // stage-input window (x_n, or y_s)
-  T wk[WK ? NP2 : 1][3];   // stage 2: k_1 on the window
-  T b0r[NP1][3];           // B0'' at the field points
-  double px[LAST ? 3 : 1]; // stage 6: x_n at the output node
-  T pk[NPKA][3];           // k_j at the output node
-  double ps[2][3];         // PART stages 5, 6: (Y6, E) or (dX, E) at the output node
+  double wx[NP2][3];      // window base (x_n, y_3 or y_5)
+  T wk[WV ? NP2 : 1][3];  // the window vector v
+  T b0r[NP1][3];          // B0'' at the field points
+  T pk[NPKA][3];          // k_j at the output node (stages 3, 4)
+  T ps[PS ? 2 : 1][3];    // stage 5: (P6, E); stage 6: (X, E) at the output node
+  // own-node values of the three committed planes hi - 2, hi - 1, hi (oldest first)
+  double cx[CX ? 3 : 1][3] = {};
+  T ck[CK1 ? 3 : 1][3] = {};
   auto load_window = [&](int pz) {
     const long long zo = (long long)zload(pz) * nxy;
 #pragma unroll
     for (int m = 0; m < 3; m++) {
-      const auto rs = plane_rsrc(wsrc + m * N + zo, nxy);
+      const auto rs = plane_rsrc(wbase + m * N + zo, nxy);
 #pragma unroll
       for (int r = 0; r < NP2; r++) wx[r][m] = bload<double>(rs, w2e[r]);
     }
-    if constexpr (WK) {
+    if constexpr (WV) {
 #pragma unroll
       for (int m = 0; m < 3; m++) {
-        const auto rs = plane_rsrc(k1p + m * N + zo, nxy);
+        const auto rs = plane_rsrc(wvec + m * N + zo, nxy);
 #pragma unroll
         for (int r = 0; r < NP2; r++) wk[r][m] = bload<T>(rs, w2e[r]);
       }
     }
   };
+  // y = base + cv v, rounded once, plus the periodic shift of a wrapped neighbour
   auto commit_window = [&](int pz) {
     const AxisIdx rz = resolve_near(pz, nz, bcz);
     const int slot = mod3(pz);
     const double shz = rz.w * g.period[2];
 #pragma unroll
     for (int r = 0; r < NP2; r++) {
-      const int e = tid + r * NTHREADS;
       const bool ok = (w2e[r] != IE);
       double v[3];
 #pragma unroll
       for (int m = 0; m < 3; m++) {
         double y = wx[r][m];
-        if constexpr (WK) y = fma(c21, (double)wk[r][m], y);
+        if constexpr (S == 2) {
+          y = y + cv * (double)wk[r][m];
+        } else if constexpr (WV) {
+          y = y + (double)wk[r][m];
+        }
         v[m] = y;
       }
       v[0] += (double)(short)(w2w[r] & 0xffff) * g.period[0];
       v[1] += (double)(w2w[r] >> 16) * g.period[1];
       v[2] += shz;
-      if (e < RY2 * RX2) {
+      if (w2o[r] >= 0) {
 #pragma unroll
-        for (int m = 0; m < 3; m++) ys[slot][m][e] = ok ? v[m] : 0.0;
+        for (int m = 0; m < 3; m++) ys[slot][m][w2o[r]] = ok ? v[m] : 0.0;
+      }
+    }
+    // the own node (window point 0) enters the carry
+#pragma unroll
+    for (int m = 0; m < 3; m++) {
+      if constexpr (CX) {
+        cx[0][m] = cx[1][m];
+        cx[1][m] = cx[2][m];
+        cx[2][m] = wx[0][m];
+      }
+      if constexpr (CK1) {
+        ck[0][m] = ck[1][m];
+        ck[1][m] = ck[2][m];
+        ck[2][m] = wk[0][m];
       }
     }
   };
@@ -380,31 +318,22 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     }
   };
   auto load_point = [&](int pz) {
-    if constexpr (PART_IN) {
-      const long long zo = (long long)zload(pz) * nxy;
-      if constexpr (LAST) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) px[m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(xn + m * N + zo, nxy), out_e);
-      }
-      const double* s0 = (S == 5) ? a.acc[0] : a.acc[1];
-#pragma unroll
-      for (int m = 0; m < 3; m++) ps[0][m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(s0 + m * N + zo, nxy), out_e);
-#pragma unroll
-      for (int m = 0; m < 3; m++)
-        ps[1][m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(a.acc[2] + m * N + zo, nxy), out_e);
-    }
+    const long long zo = (long long)zload(pz) * nxy;
     if constexpr (NPK > 0) {
-      const long long zo = (long long)zload(pz) * nxy;
-      if constexpr (LAST) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) px[m] = bload<double, RELAX_STREAM_CPOL>(plane_rsrc(xn + m * N + zo, nxy), out_e);
-      }
 #pragma unroll
       for (int j = 0; j < NPK; j++) {
-        const T* kj = static_cast<const T*>(a.k[point_k<S>(j)]);
+        const T* kj = static_cast<const T*>(a.k[j]);
 #pragma unroll
-        for (int m = 0; m < 3; m++) pk[j][m] = bload<T, RELAX_STREAM_CPOL>(plane_rsrc(kj + m * N + zo, nxy), out_e);
+        for (int m = 0; m < 3; m++) pk[j][m] = bload<T, CPOL_STREAM>(plane_rsrc(kj + m * N + zo, nxy), out_e);
       }
+    }
+    if constexpr (PS) {
+      const T* s0 = static_cast<const T*>(S == 5 ? a.sum[0] : a.sum[1]);
+      const T* s1 = static_cast<const T*>(a.sum[2]);
+#pragma unroll
+      for (int m = 0; m < 3; m++) ps[0][m] = bload<T, CPOL_STREAM>(plane_rsrc(s0 + m * N + zo, nxy), out_e);
+#pragma unroll
+      for (int m = 0; m < 3; m++) ps[1][m] = bload<T, CPOL_STREAM>(plane_rsrc(s1 + m * N + zo, nxy), out_e);
     }
   };
 
@@ -454,34 +383,23 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   auto need_lo = [&](int p) { return perz ? p - 1 : (p == 0 ? 0 : (p == nz - 1 ? p - 2 : p - 1)); };
 
   // reductions
-  double acc_E = 0.0, acc_R2 = 0.0, acc_xi = 0.0, acc_min = INFINITY, acc_null = 0.0, acc_lam = 0.0;
+  double acc_E = 0.0, acc_R2 = 0.0, acc_min = INFINITY, acc_null = 0.0, acc_lam = 0.0;
   double acc_conc = 0.0;  // DIAG: concave nodes
-  int kap_q = 1;          // DIAG: convexity of the own node of the output plane q
+  // xi: the node of largest |f|^2 / B^4 so far, kept as (|f|^2, B^4, B^2) and compared by
+  // cross-multiplication, so that the square root and the division are taken once at the end
+  double xi_F2 = 0.0, xi_B4 = 1.0, xi_B2 = 1.0;
+  int kap_q = 1;  // DIAG: convexity of the own node of the output plane q
 
   // ---- stores of one output plane (every lane issues them; masked-off lanes are dropped) ----
-  // stage 1: k_1 (or u, in a diagnostics sweep that asks for it) and the checkpoint copy of
-  // x_n; stages 2..5: k_s and y_{s+1} (PART: stage 4 y_5, Y6, X, E; stage 5 y_6, E);
-  // stage 6: x_{n+1}
-  T so_k[3] = {T(0), T(0), T(0)};
-  double so_y[3] = {0.0, 0.0, 0.0};
-  double so_p[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};  // PART sums; DIAG: B, J
+  T so_k[3] = {T(0), T(0), T(0)};    // k_s (stages 1..3), u (DIAG)
+  double so_y[3] = {0.0, 0.0, 0.0};  // x_n copy (stage 1), y_3 (stage 2), y_5 (stage 4), x_{n+1}
+  T so_s[SUMS_OUT ? 3 : 1][3] = {};  // stage 3: d_4; stage 4: P6, X, E; stage 5: P6, -, E
+  double so_p[DIAG ? 3 : 1][3] = {}; // DIAG: B, J, alpha*
+  double ycq[3] = {0.0, 0.0, 0.0};   // the stage input at the tile node of plane q
   auto store_plane = [&](int qz, bool on) {
     const long long zo = (long long)zload(qz) * nxy;
-    if constexpr (PART && (S == 4 || S == 5)) {
-      const unsigned eo = on ? out_e : IE;
-      double* dy = a.y[S - 2];
-#pragma unroll
-      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dy + m * N + zo, nxy), eo, so_y[m]);
-      if constexpr (S == 4) {
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-          for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.acc[i] + m * N + zo, nxy), eo, so_p[i][m]);
-      } else {
-#pragma unroll
-        for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.acc[2] + m * N + zo, nxy), eo, so_p[2][m]);
-      }
-    } else if constexpr (DIAG) {
+    const unsigned eo = on ? out_e : IE;
+    if constexpr (DIAG) {
       // each output goes to the caller's array, or (masked) to x[diag_buf], never written
       double* fb = const_cast<double*>(a.x[cur]);
       double* du = a.u_out ? a.u_out : fb;
@@ -501,27 +419,51 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       bstore<double>(plane_rsrc(dA + zo, nxy), eA, so_p[2][0]);
       bstore<int>(plane_rsrc(dK + zo, nxy), eK, kap_q);
     } else if constexpr (STAGE1) {
-      const unsigned ek = on ? out_e : IE;
       const unsigned ec = (on && record_ck) ? out_e : IE;
       T* dk = static_cast<T*>(a.k[0]);
       double* dc = record_ck ? a.ckpt + ck_slot * 3 * N : a.xout[0];
 #pragma unroll
-      for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), ek, so_k[m]);
+      for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), eo, so_k[m]);
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dc + m * N + zo, nxy), ec, so_y[m]);
-    } else if constexpr (!LAST) {
-      const unsigned eo = on ? out_e : IE;
-      T* dk = static_cast<T*>(a.k[S - 1]);
-      double* dy = a.y[S >= 2 ? S - 2 : 0];
+    } else if constexpr (S == 2) {
+      T* dk = static_cast<T*>(a.k[1]);
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), eo, so_k[m]);
 #pragma unroll
-      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dy + m * N + zo, nxy), eo, so_y[m]);
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.y3 + m * N + zo, nxy), eo, so_y[m]);
+    } else if constexpr (S == 3) {
+      T* dk = static_cast<T*>(a.k[2]);
+      T* dd = static_cast<T*>(a.d4);
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dk + m * N + zo, nxy), eo, so_k[m]);
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(dd + m * N + zo, nxy), eo, so_s[0][m]);
+    } else if constexpr (S == 4) {
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(a.y5 + m * N + zo, nxy), eo, so_y[m]);
+#pragma unroll
+      for (int i = 0; i < 3; i++) {
+        T* ds = static_cast<T*>(a.sum[i]);
+#pragma unroll
+        for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(ds + m * N + zo, nxy), eo, so_s[i][m]);
+      }
+    } else if constexpr (S == 5) {
+#pragma unroll
+      for (int i = 0; i < 3; i += 2) {
+        T* ds = static_cast<T*>(a.sum[i]);
+#pragma unroll
+        for (int m = 0; m < 3; m++) bstore<T>(plane_rsrc(ds + m * N + zo, nxy), eo, so_s[i][m]);
+      }
     } else {
-      const unsigned eo = on ? out_e : IE;
       double* xo = a.xout[1 - cur];
 #pragma unroll
       for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(xo + m * N + zo, nxy), eo, so_y[m]);
+    }
+    if constexpr (REC) {
+      double* dy = a.yrec[S == 4 ? 0 : 1];
+#pragma unroll
+      for (int m = 0; m < 3; m++) bstore<double>(plane_rsrc(dy + m * N + zo, nxy), eo, ycq[m]);
     }
   };
 
@@ -541,16 +483,18 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   // own-node values carried between plane steps: B at q - 1 and q; at q: F' z column,
   // 1 / det F', det F
   T Bqm[3] = {T(0), T(0), T(0)}, Bq[3] = {T(0), T(0), T(0)};
-  double Fzq[3] = {0.0, 0.0, 0.0};
-  double rDq = 0.0, Dq = 0.0;
+  T Fzq[3] = {T(0), T(0), T(0)};
+  T rDq = T(0);
+  double Dq = 0.0;
 
   for (int p = pb0; p <= z1; p++) {
     const int q = p - 1;
     const bool qout = (q >= z0 && q < z1);
     // 1. F', det F' and B on the tile + 1-node halo of plane p
     T Bp[3] = {T(0), T(0), T(0)};
-    double Fzp[3] = {0.0, 0.0, 0.0};
-    double rDp = 0.0, Dp = 0.0;
+    T Fzp[3] = {T(0), T(0), T(0)};
+    T rDp = T(0);
+    double Dp = 0.0;
     int kap_p = 1;
     if (p <= pb1) {
       const int sb = p & 1;
@@ -579,10 +523,10 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
             if (r == 0) {  // this thread's own tile node
 #pragma unroll
               for (int m = 0; m < 3; m++) {
-                Fzp[m] = F[m][2];
+                Fzp[m] = (T)F[m][2];
                 Bp[m] = B[m];
               }
-              rDp = rD;
+              rDp = (T)rD;
               Dp = D * inv8h3;
               if (STAGE1 && p >= z0 && p < z1 && gi < nx && gj < ny) {
                 // energy in FP64 from the FP64 Jacobian and B0'', weights zeta on line-tied faces
@@ -642,14 +586,32 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     load_b0(p + 1 <= pb1 ? p + 1 : pb1);
     // x and y columns of F' and the stage input at the tile node of plane q, read before
     // the barrier: the commit below reuses plane q's ring slot
-    double Fxy[3][3], ycq[3];
+    T Fxy[3][2];
     if (qout) {
-      jac_xy(ty + 2, tx + 2, q, gi_t, gj_t, Fxy);
+      double Ft[3][3];
+      jac_xy(ty + 2, tx + 2, q, gi_t, gj_t, Ft);
       const int o = (ty + 2) * RX2 + tx + 2, sq = mod3(q);
 #pragma unroll
-      for (int m = 0; m < 3; m++) ycq[m] = ys[sq][m][o];
+      for (int m = 0; m < 3; m++) {
+        Fxy[m][0] = (T)Ft[m][0];
+        Fxy[m][1] = (T)Ft[m][1];
+        ycq[m] = ys[sq][m][o];
+      }
     }
     __syncthreads();
+
+    // carried own-node values of plane q (the carry holds planes hi - 2, hi - 1, hi), taken
+    // before the commit below moves it on
+    double xq[3] = {0.0, 0.0, 0.0};
+    T kq[3] = {T(0), T(0), T(0)};
+    if constexpr (CX) {
+      const int cidx = q - (hi - 2);
+#pragma unroll
+      for (int m = 0; m < 3; m++) {
+        xq[m] = cidx == 0 ? cx[0][m] : (cidx == 1 ? cx[1][m] : cx[2][m]);
+        if constexpr (CK1) kq[m] = cidx == 0 ? ck[0][m] : (cidx == 1 ? ck[1][m] : ck[2][m]);
+      }
+    }
 
     // 2. commit the stage-input plane that field(p + 1) needs; issue the next one
     if (p + 1 <= pb1 && need_hi(p + 1) > hi) {
@@ -683,9 +645,9 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
         T Fq[3][3];
 #pragma unroll
         for (int m = 0; m < 3; m++) {
-          Fq[m][0] = (T)Fxy[m][0];
-          Fq[m][1] = (T)Fxy[m][1];
-          Fq[m][2] = (T)Fzq[m];
+          Fq[m][0] = Fxy[m][0];
+          Fq[m][1] = Fxy[m][1];
+          Fq[m][2] = Fzq[m];
         }
         // c'_q = (F' e_b) . G'_a - (F' e_a) . G'_b, (a, b, q) = (y, z, x), (z, x, y), (x, y, z)
         T cq[3];
@@ -695,10 +657,9 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                 (Fq[0][2] * G[0][0] + Fq[1][2] * G[0][1] + Fq[2][2] * G[0][2]);
         cq[2] = Fq[0][1] * G[0][0] + Fq[1][1] * G[0][1] + Fq[2][1] * G[0][2] -
                 (Fq[0][0] * G[1][0] + Fq[1][0] * G[1][1] + Fq[2][0] * G[1][2]);
-        const T iD = (T)rDq;
         T J[3];
 #pragma unroll
-        for (int m = 0; m < 3; m++) J[m] = (Fq[m][0] * cq[0] + Fq[m][1] * cq[1] + Fq[m][2] * cq[2]) * iD;
+        for (int m = 0; m < 3; m++) J[m] = (Fq[m][0] * cq[0] + Fq[m][1] * cq[1] + Fq[m][2] * cq[2]) * rDq;
         if constexpr (DIAG) {
 #pragma unroll
           for (int m = 0; m < 3; m++) so_p[1][m] = J[m];
@@ -719,8 +680,12 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
           const double B2 = (double)Bq[0] * Bq[0] + (double)Bq[1] * Bq[1] + (double)Bq[2] * Bq[2];
           acc_R2 += Dq * F2;
           if (B2 > tau_B2) {
-            const double ratio = sqrt(F2) / B2;
-            acc_xi = (ratio > acc_xi || ratio != ratio) ? ratio : acc_xi;
+            const double B4 = B2 * B2;
+            if (F2 * xi_B4 > xi_F2 * B4 || F2 != F2) {
+              xi_F2 = F2;
+              xi_B4 = B4;
+              xi_B2 = B2;
+            }
           } else {
             acc_null += 1.0;
           }
@@ -733,58 +698,62 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
           so_k[m] = diag_only ? (T)((double)u[m] * sc) : u[m];
           so_y[m] = ycq[m];
         }
-      } else if constexpr (PART && S == 4) {
+      } else if constexpr (S == 2) {
+        // y_3 = x_n + dt (a_31 k_1 + a_32 k_2), from the own node's x_n and k_1 of plane q
 #pragma unroll
         for (int m = 0; m < 3; m++) {
-          double y = ycq[m], y6 = ycq[m], xs = 0.0, es = 0.0;
-#pragma unroll
-          for (int j = 0; j < 3; j++) {
-            const double kj = pk[j][m];
-            y = fma(cy[j], kj, y);
-            y6 = fma(cp[0][j], kj, y6);
-            xs = fma(cp[1][j], kj, xs);
-            es = fma(cp[2][j], kj, es);
-          }
-          const double k4 = u[m];
-          so_y[m] = fma(cys, k4, y);
-          so_p[0][m] = fma(cps[0], k4, y6);
-          so_p[1][m] = fma(cps[1], k4, xs);
-          so_p[2][m] = fma(cps[2], k4, es);
-        }
-      } else if constexpr (PART && S == 5) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-          so_y[m] = fma(dt * CK::a[5][4], (double)u[m], ps[0][m]);
-          so_p[2][m] = fma(dt * (CK::b5[4] - CK::b4[4]), (double)u[m], ps[1][m]);
-        }
-      } else if constexpr (PART && LAST) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-          so_y[m] = px[m] + fma(dt * CK::b5[5], (double)u[m], ps[0][m]);
-          const double e = fma(dt * (CK::b5[5] - CK::b4[5]), (double)u[m], ps[1][m]);
-          const double err = tile_ok ? fabs(e) : 0.0;
-          acc_lam = (err > acc_lam || err != err) ? err : acc_lam;
-        }
-      } else if constexpr (!LAST) {
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-          double y = ycq[m];
-#pragma unroll
-          for (int j = 0; j < NPK; j++) y = fma(cy[j], (double)pk[j][m], y);
-          so_y[m] = fma(cys, (double)u[m], y);
+          const double d3 = fma(dt * CK::a[2][1], (double)u[m], (dt * CK::a[2][0]) * (double)kq[m]);
+          so_y[m] = xq[m] + d3;
           so_k[m] = u[m];
         }
-      } else {
-        // x_{n+1} = x_n + dt sum b5_s k_s;  err = dt sum (b5_s - b4_s) k_s
+      } else if constexpr (S == 3) {
+        // d_4 = dt (a_41 k_1 + a_42 k_2 + a_43 k_3)
 #pragma unroll
         for (int m = 0; m < 3; m++) {
-          const double v1 = pk[0][m], v3 = pk[1][m], v4 = pk[2][m], v5 = pk[3][m], v6 = (double)u[m];
-          const double s5 = CK::b5[0] * v1 + CK::b5[2] * v3 + CK::b5[3] * v4 + CK::b5[5] * v6;
-          const double se = (CK::b5[0] - CK::b4[0]) * v1 + (CK::b5[2] - CK::b4[2]) * v3 +
-                            (CK::b5[3] - CK::b4[3]) * v4 + (CK::b5[4] - CK::b4[4]) * v5 +
-                            (CK::b5[5] - CK::b4[5]) * v6;
-          so_y[m] = px[m] + dt * s5;
-          const double err = tile_ok ? fabs(dt * se) : 0.0;
+          double d4 = (dt * CK::a[3][0]) * (double)pk[0][m];
+          d4 = fma(dt * CK::a[3][1], (double)pk[1][m], d4);
+          d4 = fma(dt * CK::a[3][2], (double)u[m], d4);
+          so_k[m] = u[m];
+          so_s[0][m] = (T)d4;
+        }
+      } else if constexpr (S == 4) {
+        // y_5 = x_n + d_5, and the partial sums of k_1..k_4 the last two stages need
+        // (b5_2 = b4_2 = 0: k_2 enters neither X nor E)
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          const double k1 = pk[0][m], k2 = pk[1][m], k3 = pk[2][m], k4 = u[m];
+          double d5 = (dt * CK::a[4][0]) * k1;
+          d5 = fma(dt * CK::a[4][1], k2, d5);
+          d5 = fma(dt * CK::a[4][2], k3, d5);
+          d5 = fma(dt * CK::a[4][3], k4, d5);
+          double p6 = (dt * CK::a[5][0]) * k1;
+          p6 = fma(dt * CK::a[5][1], k2, p6);
+          p6 = fma(dt * CK::a[5][2], k3, p6);
+          p6 = fma(dt * CK::a[5][3], k4, p6);
+          double xs = (dt * CK::b5[0]) * k1;
+          xs = fma(dt * CK::b5[2], k3, xs);
+          xs = fma(dt * CK::b5[3], k4, xs);
+          double es = (dt * (CK::b5[0] - CK::b4[0])) * k1;
+          es = fma(dt * (CK::b5[2] - CK::b4[2]), k3, es);
+          es = fma(dt * (CK::b5[3] - CK::b4[3]), k4, es);
+          so_y[m] = xq[m] + d5;
+          so_s[0][m] = (T)p6;
+          so_s[1][m] = (T)xs;
+          so_s[2][m] = (T)es;
+        }
+      } else if constexpr (S == 5) {
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          so_s[0][m] = (T)fma(dt * CK::a[5][4], (double)u[m], (double)ps[0][m]);
+          so_s[2][m] = (T)fma(dt * (CK::b5[4] - CK::b4[4]), (double)u[m], (double)ps[1][m]);
+        }
+      } else {
+        // x_{n+1} = x_n + (X + dt b5_6 k_6);  error E + dt (b5_6 - b4_6) k_6
+#pragma unroll
+        for (int m = 0; m < 3; m++) {
+          so_y[m] = xq[m] + fma(dt * CK::b5[5], (double)u[m], (double)ps[0][m]);
+          const double e = fma(dt * (CK::b5[5] - CK::b4[5]), (double)u[m], (double)ps[1][m]);
+          const double err = tile_ok ? fabs(e) : 0.0;
           acc_lam = (err > acc_lam || err != err) ? err : acc_lam;
         }
       }
@@ -807,6 +776,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   // ---- workgroup reductions -> partial records -----------------------------------------
   const int wave = tid >> 6, lane = tid & 63;
   if (STAGE1) {
+    const double acc_xi = sqrt(xi_F2) / xi_B2;
     const double e = wave_sum(acc_E), r2 = wave_sum(acc_R2), xi = wave_max(acc_xi), mn = wave_min(acc_min),
                  nl = wave_sum(acc_null), cc = wave_sum(acc_conc);
     if (lane == 0) {
@@ -864,12 +834,29 @@ hipError_t launch_stage_t(int s, const SweepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// the forward replay of the reverse pass (FP64): stages 4 and 6 also store their input
+template <bool XYP>
+hipError_t launch_stage_rec_t(int s, const SweepArgs& a, hipStream_t st) {
+  const dim3 grid(a.g.nblocks), block(NTHREADS);
+  switch (s) {
+    case 4: hipLaunchKernelGGL((stage_kernel<4, false, XYP, false, true>), grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((stage_kernel<6, false, XYP, false, true>), grid, block, 0, st, a); break;
+    default: return launch_stage_t<false, XYP>(s, a, st);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st) {
   const bool xyp = (a.g.bc[0] == BC_PERIODIC && a.g.bc[1] == BC_PERIODIC);
   if (mixed) return xyp ? launch_stage_t<true, true>(s, a, st) : launch_stage_t<true, false>(s, a, st);
   return xyp ? launch_stage_t<false, true>(s, a, st) : launch_stage_t<false, false>(s, a, st);
+}
+
+hipError_t launch_stage_rec(int s, const SweepArgs& a, hipStream_t st) {
+  const bool xyp = (a.g.bc[0] == BC_PERIODIC && a.g.bc[1] == BC_PERIODIC);
+  return xyp ? launch_stage_rec_t<true>(s, a, st) : launch_stage_rec_t<false>(s, a, st);
 }
 
 hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st) {

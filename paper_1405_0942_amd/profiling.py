@@ -55,7 +55,7 @@ def read_counter(run_dir: str, counter: str):
 
 
 def _stage_of(name: str):
-    m = re.search(r"stage_kernel<(\d), (false|true), (false|true)(?:, false)?>", name)
+    m = re.search(r"stage_kernel<(\d), (false|true), (false|true)(?:, false(?:, (?:false|true))?)?>", name)
     if not m:
         return None
     return int(m.group(1)), m.group(2) == "true"

@@ -15,8 +15,10 @@ n = 17, 33 also in the FP32-mixed mode.  xi is not compared: it keeps falling wi
 length and depends on Lambda0 (the paper says so, Sec. 4.1), neither of which the paper
 states; it must only show that the field relaxed.  RELAX_ISOHELIX_FULL=1 adds n = 129 for
 phi = pi/4.  At n = 129 the pi/2 and pi runs (FP64 and FP32-mixed alike) reach smaller
-eps* and sigma_B than the paper's single-precision rows print (by up to 3x), so those rows are
-not compared.
+eps* and sigma_B than the paper's single-precision rows print (by up to 3x).  The cause of
+that deviation is not known (one hypothesis: the single precision of those runs of the paper,
+or run lengths it does not give), so those rows are reported in the design notes and not
+compared.
 """
 import os
 

@@ -12,9 +12,11 @@ eps* is compared with the values the paper prints in Table 2
 xi is not compared, for the reason the IsoHelix runs give (it keeps falling with run length
 and depends on Lambda0).  The relaxed grid has a few concave nodes at n = 17 (Sec. 4.4: high
 distortion makes concave cells, mostly at low resolution) and none from n = 33 on.
-RELAX_PONTIN09_FULL=1 adds n = 129, where the paper's eps* (6.4e-4, hardly below its 65 row)
-looks like a single-precision floor: these FP64 runs reach 5.4e-5 there, so that row is only
-checked as an upper bound.
+RELAX_PONTIN09_FULL=1 adds n = 129.  There these FP64 runs reach eps* = 5.4e-5 against the
+paper's 6.4e-4 (hardly below its own n = 65 row).  The cause of that deviation is not known
+(one hypothesis: a single-precision floor of the paper's run, whose precision Table 2 does
+not mark), so the n = 129 value is reported and checked only for the fall with resolution,
+not against the paper's number.
 """
 import math
 import os
@@ -69,10 +71,8 @@ def test_pontin09_relaxed_state_matches_table2():
             assert fin["concave"] == 0  # only the coarsest grid has concave nodes
         eps[n] = epsilon_star(g, alpha)
         banner(f"n {n}: eps* {eps[n]:.2e} ({steps} steps) | Table 2: eps* {paper[n][1]:.1e}")
-        if n < 129:
+        if n < 129:  # the 129 row deviates for a reason not known (module text): reported only
             assert 1 / 1.3 < eps[n] / paper[n][1] < 1.3, (n, eps[n], paper[n][1])
-        else:  # the paper's single-precision 129 row hardly improves on its 65 row: upper bound
-            assert eps[n] < 1.3 * paper[n][1], (n, eps[n], paper[n][1])
         assert fin["xi"] < 1e-4
     ns = sorted(eps)
     for a, b in zip(ns, ns[1:]):
