@@ -118,6 +118,20 @@ int relax_step(void* ctx, int K, relax_diag* host_diag, int* steps_done);
  * min_det and concave (Sec. 3.2.3); Lambda and rejects are 0. */
 int relax_diagnostics(void* ctx, relax_diag* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc) and hold no context: the diagnostics of
+ * relax_diagnostics for positions d_x and initial field d_B0 given directly ([3][nz][ny][nx]
+ * FP64 device arrays, read only), with the configuration cfg (n, h, bc, gamma, xi_null_tau;
+ * dt0 is reported as dt, t as 0).  The result equals relax_diagnostics of a context created
+ * by relax_init(cfg, ..., d_x, d_B0, ...).  No allocation: the call's device scratch is a
+ * fixed array of the library (1 MiB per device, held until the process ends), enough for
+ * sweeps of at most 16384 workgroups of 64 x 8 nodes (for example every grid of up to
+ * 512 x 512 x 512 nodes); larger grids return RELAX_E_SPACE before any GPU work.  Calls on
+ * one device share that scratch: calls that overlap on one device (several host threads, or
+ * several streams) race and must not be made.  Blocks until done. */
+int relax_diagnostics_noalloc(const relax_config* cfg, const double* d_x, const double* d_B0, void* hip_stream,
+                              relax_diag* out);
+
 /* Velocity u = gamma J x B of the current positions (Sec. 1, eq. "magneto friction", with
  * J the mimetic current of Sec. 2.2), evaluated in FP64 (also for a mixed-precision
  * context) into d_u_out (device, [3][nz][ny][nx], overwritten; zero on line-tied faces).

@@ -24,8 +24,8 @@ RELAX_LINE_TIED, RELAX_PERIODIC = 0, 1
 RELAX_FP64, RELAX_FP32_MIXED = 0, 1
 
 # every symbol include/relax.h declares
-EXPORTS = ("relax_workspace_bytes", "relax_init", "relax_step", "relax_diagnostics", "relax_velocity",
-           "relax_fields", "relax_monitors", "relax_backward",
+EXPORTS = ("relax_workspace_bytes", "relax_init", "relax_step", "relax_diagnostics", "relax_diagnostics_noalloc",
+           "relax_velocity", "relax_fields", "relax_monitors", "relax_backward",
            "relax_get_state", "relax_set_state", "relax_profile", "relax_stream_probe",
            "relax_strerror",
            "relax_last_error",
@@ -78,6 +78,7 @@ def lib():
     L.relax_init.argtypes = [C.POINTER(relax_config), C.c_int, vp, vp, vp, C.c_size_t, vp, C.POINTER(vp)]
     L.relax_step.argtypes = [vp, C.c_int, C.POINTER(relax_diag), C.POINTER(C.c_int)]
     L.relax_diagnostics.argtypes = [vp, C.POINTER(relax_diag)]
+    L.relax_diagnostics_noalloc.argtypes = [C.POINTER(relax_config), vp, vp, vp, C.POINTER(relax_diag)]
     L.relax_velocity.argtypes = [vp, vp]
     L.relax_fields.argtypes = [vp, vp, vp]
     L.relax_monitors.argtypes = [vp, vp, vp]
@@ -94,8 +95,8 @@ def lib():
     L.relax_last_error.restype = C.c_char_p
     L.relax_destroy.argtypes = [vp]
     L.relax_destroy.restype = None
-    for name in ("relax_init", "relax_step", "relax_diagnostics", "relax_velocity", "relax_fields", "relax_monitors",
-                 "relax_backward", "relax_get_state",
+    for name in ("relax_init", "relax_step", "relax_diagnostics", "relax_diagnostics_noalloc", "relax_velocity",
+                 "relax_fields", "relax_monitors", "relax_backward", "relax_get_state",
                  "relax_set_state"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -125,6 +126,12 @@ def relax_step(ctx, K, host_diag=None):
 def relax_diagnostics(ctx):
     d = relax_diag()
     rc = lib().relax_diagnostics(ctx, C.byref(d))
+    return rc, d
+
+
+def relax_diagnostics_noalloc(cfg, d_x, d_B0, stream):
+    d = relax_diag()
+    rc = lib().relax_diagnostics_noalloc(C.byref(cfg), d_x, d_B0, stream, C.byref(d))
     return rc, d
 
 

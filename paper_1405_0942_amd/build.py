@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librelax.so")
-SOURCES = ["stage.hip", "adjoint.hip", "control.hip", "stream.hip", "relax.cpp"]
+SOURCES = ["stage.hip", "adjoint.hip", "control.hip", "stream.hip", "noalloc.hip", "relax.cpp"]
 ARCH = os.environ.get("RELAX_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -94,6 +94,11 @@ int fail(Ctx* c, int code, const std::string& msg) {
       return fail((ctx), RELAX_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+}  // namespace
+
+// configuration checks and the sweep geometry (also used by noalloc.hip)
+namespace relax {
+
 bool valid_config(const relax_config* c) {
   if (!c) return false;
   for (int a = 0; a < 3; a++) {
@@ -160,6 +165,10 @@ Geometry make_geometry(const relax_config* c) {
   g.nblocks = g.tiles[0] * g.tiles[1] * g.tiles[2];
   return g;
 }
+
+}  // namespace relax
+
+namespace {
 
 Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   Layout L{};
@@ -245,6 +254,7 @@ SweepArgs sweep_args(Ctx* c) {
   a.diag_buf = 0;
   a.u_out = nullptr;
   a.u_det_scale = 0.0;
+  a.b0_mul[0] = a.b0_mul[1] = a.b0_mul[2] = 1.0;
   return a;
 }
 

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "relax.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -84,6 +86,8 @@ struct SweepArgs {
   double* J_out;       // diagnostics sweep only: if not null, receives J(x) [3][N] (0 on line-tied faces)
   double* alpha_out;   // diagnostics sweep only: if not null, receives alpha* = J.B / B^2 [N]
   int* kappa_out;      // diagnostics sweep only: if not null, receives the convexity +1 / -1 [N]
+  double b0_mul[3];    // diagnostics sweep only: factors on B0 as loaded (1 for the prescaled
+                       // copy B0''; 4 h_b h_c for a caller's unscaled B0)
 };
 
 // Arguments of the reverse-mode sweeps (adjoint.hip).  FP64 throughout.
@@ -120,6 +124,13 @@ struct CK {
   static constexpr double b4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0,
                                    277.0 / 14336.0, 1.0 / 4.0};
 };
+
+// ------------------------------------------------------------------------------------------
+// Host helpers implemented in relax.cpp
+// ------------------------------------------------------------------------------------------
+bool valid_config(const relax_config* c);          // every field in range
+int choose_tz(const relax_config* c, int tiles_xy);  // z-chunk length
+Geometry make_geometry(const relax_config* c);     // tiles, chunks and scale factors
 
 // ------------------------------------------------------------------------------------------
 // Launchers implemented in the kernel translation units

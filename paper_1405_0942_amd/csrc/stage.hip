@@ -510,7 +510,12 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
             jacobian(r1 + 1, c1 + 1, p, gi, gj, F);
             const double D = det3(F);
             const double rD = rcp_nr(D);
-            const T q0 = b0r[r][0], q1 = b0r[r][1], q2 = b0r[r][2];
+            T q0 = b0r[r][0], q1 = b0r[r][1], q2 = b0r[r][2];
+            if constexpr (DIAG) {
+              q0 *= a.b0_mul[0];
+              q1 *= a.b0_mul[1];
+              q2 *= a.b0_mul[2];
+            }
             if constexpr (MIXED) {
               const float fi = (float)rD;
 #pragma unroll

@@ -113,3 +113,17 @@ def test_config_struct_layout_matches_header():
     # adaptive, record, checkpoint_every int, xi_null_tau double
     assert ctypes.sizeof(R.relax_config) == 12 + 4 + 24 + 12 + 4 + 32 + 12 + 4 + 8 + 8
     assert ctypes.sizeof(R.relax_diag) == 7 * 8 + 8
+
+
+def test_noalloc_rejects_without_touching_the_gpu():
+    """relax_diagnostics_noalloc checks its arguments and its scratch limit (16384 workgroups
+    of 64 x 8 nodes) on the host, before any GPU work."""
+    c = _cfg()
+    assert R.relax_diagnostics_noalloc(c, 0, 1 << 20, None)[0] == R.RELAX_E_ARG
+    bad = _cfg()
+    bad.n[0] = 3
+    assert R.relax_diagnostics_noalloc(bad, 1 << 20, 1 << 20, None)[0] == R.RELAX_E_ARG
+    big = _cfg()
+    big.n[0], big.n[1], big.n[2] = 4096, 4096, 4  # 32768 tiles of 64 x 8
+    assert R.relax_workspace_bytes(big) > 0
+    assert R.relax_diagnostics_noalloc(big, 1 << 20, 1 << 20, None)[0] == R.RELAX_E_SPACE
