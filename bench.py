@@ -40,18 +40,18 @@ ALGO_FP64 = [72, 96, 120, 144, 168, 192]
 ALGO_MIXED = [48, 60, 72, 84, 96, 120]
 ALGO_STEP = {"fp64": sum(ALGO_FP64), "fp32-mixed": sum(ALGO_MIXED)}
 
-# What this library's sweeps move per node (its own design, used only for the "design" keys):
-# stages 2..5 also store the next stage input y_{s+1}; in FP64 stage 4 stores the partial sums
-# Y6, dX, E that stages 5 and 6 read instead of k_1..k_4.
+# What this library's sweeps move per node (its own design, used only for the "design" keys).
+# Every stage input is x_n plus one increment rounded once; a window holds at most two vectors:
 #   stage 1: x_n, B0 -> k_1
-#   stage 2: x_n, k_1, B0, k_1 at the node -> k_2, y_3
-#   stage 3: y_3, B0, k_1, k_2 at the node -> k_3, y_4
-# FP64: stage 4: y_4, B0, k_1..k_3 -> y_5, Y6, dX, E; stage 5: y_5, B0, Y6, E -> y_6, E;
-#       stage 6: y_6, B0, x_n, dX, E -> x_{n+1}
-# FP32-mixed: stage s = 4, 5: y_s, B0, k_1..k_{s-1} -> k_s, y_{s+1};
-#       stage 6: y_6, B0, x_n, k_1, k_3, k_4, k_5 -> x_{n+1}
-DESIGN_FP64 = [72, 144, 144, 216, 144, 144]
-DESIGN_MIXED = [48, 96, 96, 108, 120, 132]
+#   stage 2: x_n, k_1, B0 -> k_2, y_3
+#   stage 3: y_3, B0, k_1, k_2 at the node -> k_3, d_4
+#   stage 4: x_n, d_4, B0, k_1..k_3 at the node -> y_5, P6, X, E
+#   stage 5: y_5, B0, P6, E -> P6 (now d_6), E
+#   stage 6: x_n, d_6, B0, X, E -> x_{n+1}
+# FP64: every vector 24 B (864 B per attempt); FP32-mixed: x_n, y_3, y_5 and x_{n+1} 24 B, the
+# k_j, d_4, the partial sums and B0 12 B (540 B per attempt).
+DESIGN_FP64 = [72, 120, 144, 240, 144, 144]
+DESIGN_MIXED = [48, 84, 84, 144, 84, 96]
 
 
 def log(msg):

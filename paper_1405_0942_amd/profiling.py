@@ -24,7 +24,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/stage.hip", "csrc/relax_device.h")
+KERNEL_SOURCES = ("csrc/stage.hip", "csrc/sweep_common.h", "csrc/relax_device.h")
 COPY_BYTES = 1 << 30
 
 
@@ -138,7 +138,8 @@ def kernel_stats(run_dir: str):
 
 
 def _short(name: str) -> str:
-    name = name.replace("relax::(anonymous namespace)::", "").replace("(relax::SweepArgs)", "")
+    name = name.replace("relax::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+    name = name.replace("(relax::SweepArgs)", "")
     name = re.sub(r"^void ", "", name)
     return re.sub(r"\(.*\)$", "", name) if "stage_kernel" not in name else name
 
