@@ -12,6 +12,7 @@ library raises :class:`RelaxUnavailable`.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -64,14 +65,31 @@ _lib = None
 def lib():
     """The loaded librelax.so (raises RelaxUnavailable if it cannot be loaded)."""
     global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RelaxUnavailable(f"{LIB_PATH} is not built (run python -m paper_1405_0942_amd.build)")
+    if _lib is None:
+        _lib = _load(LIB_PATH)
+    return _lib
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every call of this binding to another build of the library (the tests' 64 x 4
+    tile build) inside the block."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
     try:
-        L = C.CDLL(LIB_PATH)
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def _load(path: str):
+    if not os.path.exists(path):
+        raise RelaxUnavailable(f"{path} is not built (run python -m paper_1405_0942_amd.build)")
+    try:
+        L = C.CDLL(path)
     except OSError as e:  # pragma: no cover - depends on the machine
-        raise RelaxUnavailable(f"cannot load {LIB_PATH}: {e}") from e
+        raise RelaxUnavailable(f"cannot load {path}: {e}") from e
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     L.relax_workspace_bytes.argtypes = [C.POINTER(relax_config), C.c_int]
     L.relax_workspace_bytes.restype = C.c_size_t
@@ -99,7 +117,6 @@ def lib():
                  "relax_fields", "relax_monitors", "relax_backward", "relax_get_state",
                  "relax_set_state"):
         getattr(L, name).restype = C.c_int
-    _lib = L
     return L
 
 

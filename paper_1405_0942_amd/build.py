@@ -31,11 +31,11 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, tile_y: int) -> str:
     path = os.path.join(CSRC, src)
-    obj = os.path.join(CSRC, src + ".o")
+    obj = os.path.join(CSRC, f"{src}.ty{tile_y}.o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, *lang, "-c", path, "-o", obj]
+    cmd = [HIPCC, *FLAGS, f"-DRELAX_TILE_Y={tile_y}", *lang, "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,20 +46,31 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+# The same library with 64 x 4 workgroup tiles instead of 64 x 8: built only so that a test
+# can check that per-node results do not depend on the tile shape (an LDS race or a halo
+# mistake would show there).
+LIB_TY4 = os.path.join(HERE, "librelax_ty4.so")
+
+
+def _build_one(path: str, tile_y: int, verbose: bool) -> str:
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, verbose, tile_y), SOURCES))
+    tmp = path + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, path)
     for o in objs:
         os.remove(o)
-    return LIB
+    return path
+
+
+def build(verbose: bool = False) -> str:
+    _build_one(LIB_TY4, 4, verbose)
+    return _build_one(LIB, 8, verbose)
 
 
 if __name__ == "__main__":

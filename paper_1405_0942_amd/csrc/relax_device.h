@@ -15,8 +15,11 @@ namespace relax {
 // Tiling of the fused stage sweep.  One workgroup owns a TX x TY column of nodes in (x, y)
 // and marches up a z-chunk of TZ planes; one wave64 covers one x-row of the tile.
 // ------------------------------------------------------------------------------------------
+#ifndef RELAX_TILE_Y
+#define RELAX_TILE_Y 8  // another height is built only to check that results do not depend on it
+#endif
 constexpr int TX = 64;
-constexpr int TY = 8;
+constexpr int TY = RELAX_TILE_Y;
 constexpr int NTHREADS = TX * TY;  // 512 = 8 waves; one workgroup per CU (LDS: 91 KB in FP64)
 constexpr int RX2 = TX + 4, RY2 = TY + 4;  // stage-input window (2-node halo)
 constexpr int RX1 = TX + 2, RY1 = TY + 2;  // pulled-back field window (1-node halo)
