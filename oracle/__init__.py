@@ -9,6 +9,7 @@ object with attributes n (nx, ny, nz), h (hx, hy, hz) and bc (0 line-tied, 1 per
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 
@@ -47,6 +48,8 @@ def lib():
     L.orc_rhs_sampled.argtypes = [i3, d3, i3, C.c_double, _dp, _dp, C.c_long,
                                   np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS"), _dp]
     L.orc_rhs_sampled.restype = C.c_int
+    L.orc_set_curl.argtypes = [C.c_int]
+    L.orc_set_curl.restype = C.c_int
     L.orc_threads.argtypes = []
     L.orc_threads.restype = C.c_int
     L.orc_set_threads.argtypes = [C.c_int]
@@ -148,6 +151,21 @@ def ck_attempt(grid, x, B0, dt, gamma=1.0, want_k=False):
     k = np.empty((6,) + x.shape) if want_k else None
     _check(lib().orc_ck_attempt(*_g(grid), gamma, x, B0, float(dt), xn, C.byref(lam), _ptr(k)))
     return (xn, lam.value, k) if want_k else (xn, lam.value)
+
+
+CURL_NN, CURL_NNN = 0, 1
+
+
+@contextlib.contextmanager
+def curl(kind: int):
+    """Inside the block every call computes the current with the given operator: CURL_NN, the
+    nearest-neighbour loops of Sec. 2.2 (the default), or CURL_NNN, the next-nearest-neighbour
+    octilateral of Sec. 2.3."""
+    _check(lib().orc_set_curl(int(kind)))
+    try:
+        yield
+    finally:
+        lib().orc_set_curl(CURL_NN)
 
 
 def threads() -> int:

@@ -22,6 +22,9 @@
  *   area vector sum of four triangles             (Sec. 2.2, eqs. "four surfaces",
  *                                                  "sum of triangles")
  *   3x3 solve of J . n A = circulation            (Sec. 2.2, eq. "current matrix equation")
+ *   or, selected by orc_set_curl(1), the next-nearest-neighbour loops over the octilateral
+ *   of the eight in-plane ring neighbours          (Sec. 2.3, eqs. "eight surfaces",
+ *                                                  "sum of eight triangles")
  *   u = gamma J x B                               (Sec. 1, eq. "magneto friction")
  *   Cash-Karp RK5(4) + step-size rule             (Sec. 2.4, eq. "time stepping")
  *   line-tied / periodic boundaries               (Sec. 2.5)
@@ -43,6 +46,10 @@
  *      the new step; when Lambda == 0 the step grows by 5x.
  *   R16 convexity: a node is concave when any of its trihedra fails the sign test; trihedra
  *      reaching beyond a line-tied face are not formed.
+ *   R19 octilateral (Sec. 2.3; its figure is missing): vertices 1..8 are the ring neighbours
+ *      p+e_a, p+e_a+e_b, p+e_b, p-e_a+e_b, p-e_a, p-e_a-e_b, p-e_b, p+e_a-e_b (the edge
+ *      points odd, the diagonal points even); dx_r = x(V_r+1) - x(V_r); dx_A..dx_D are the
+ *      edges of the quadrilateral through the diagonal points, V2 -> V4 -> V6 -> V8 -> V2.
  */
 #include <math.h>
 #include <omp.h>
@@ -216,9 +223,90 @@ static void cross(const real_t a[3], const real_t b[3], real_t out[3]) {
   out[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+/* current operator: 0 = nearest-neighbour loops (Sec. 2.2), 1 = next-nearest-neighbour
+ * octilateral loops (Sec. 2.3) */
+static int g_curl = 0;
+
+/* B at the node p + d, read from B or (B == NULL) pulled back from B0 on the spot */
+static void vertex_field(const grid_t *g, const real_t *x, const real_t *B, const real_t *B0, long m, real_t out[3]) {
+  const long N = g->N;
+  if (B) {
+    for (int c = 0; c < 3; c++) out[c] = B[c * N + m];
+  } else {
+    int q[3] = {(int)(m % g->n[0]), (int)((m / g->n[0]) % g->n[1]), (int)(m / ((long)g->n[0] * g->n[1]))};
+    field_at(g, x, B0, q, out, NULL);
+  }
+}
+
+/* Next-nearest-neighbour mimetic current at an interior node (Sec. 2.3).  For each plane
+ * (a, b), q the third axis, the loop runs over the eight ring neighbours (reading R19):
+ *   circulation C_q = sum_{r=1..8} B_r . dx_r, B_r = (B(V_r) + B(V_r+1))/2
+ *   area vector N_q = (dx2 x dx3 + dx4 x dx5 + dx6 x dx7 + dx8 x dx1)/2
+ *                   + (dxA x dxB + dxB x dxC + dxC x dxD + dxD x dxA)/4
+ * (the four triangles at the edge points and the quadrilateral through the diagonal points,
+ * eq. "eight surfaces"), and J solves J . N_q = C_q as in Sec. 2.2. */
+static void octilateral_current(const grid_t *g, const real_t *x, const real_t *B, const real_t *B0, const int p[3],
+                                real_t J[3]) {
+  const long N = g->N;
+  static const int RING[8][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, -1}};
+  real_t M[3][3], C[3];
+  for (int q = 0; q < 3; q++) {
+    const int a = PLANE_AB[q][0], b = PLANE_AB[q][1];
+    real_t V[8][3], BV[8][3];
+    for (int r = 0; r < 8; r++) {
+      int off[3] = {0, 0, 0};
+      off[a] = RING[r][0];
+      off[b] = RING[r][1];
+      double s[3];
+      long m = neighbour(g, p, off, s);
+      for (int c = 0; c < 3; c++) V[r][c] = x[c * N + m] + s[c];
+      vertex_field(g, x, B, B0, m, BV[r]);
+    }
+    real_t dx[8][3], circ = 0.0;
+    for (int r = 0; r < 8; r++) {
+      const int r1 = (r + 1) % 8;
+      for (int c = 0; c < 3; c++) {
+        dx[r][c] = V[r1][c] - V[r][c];
+        circ += 0.5 * (BV[r][c] + BV[r1][c]) * dx[r][c];
+      }
+    }
+    /* dx_A..dx_D: V2 -> V4 -> V6 -> V8 -> V2 (0-based vertices 1, 3, 5, 7) */
+    real_t dq[4][3];
+    for (int t = 0; t < 4; t++) {
+      const int v0 = 2 * t + 1, v1 = (2 * t + 3) % 8;
+      for (int c = 0; c < 3; c++) dq[t][c] = V[v1][c] - V[v0][c];
+    }
+    real_t nA[3] = {0.0, 0.0, 0.0}, tri[3];
+    /* the triangles at the edge points: dx2 x dx3, dx4 x dx5, dx6 x dx7, dx8 x dx1 (1-based) */
+    for (int t = 0; t < 4; t++) {
+      cross(dx[2 * t + 1], dx[(2 * t + 2) % 8], tri);
+      for (int c = 0; c < 3; c++) nA[c] += 0.5 * tri[c];
+    }
+    /* the quadrilateral through the diagonal points */
+    for (int t = 0; t < 4; t++) {
+      cross(dq[t], dq[(t + 1) % 4], tri);
+      for (int c = 0; c < 3; c++) nA[c] += 0.25 * tri[c];
+    }
+    for (int c = 0; c < 3; c++) M[q][c] = nA[c];
+    C[q] = circ;
+  }
+  real_t dM = det3(M);
+  real_t inv = 1.0 / dM;
+  for (int c = 0; c < 3; c++) {
+    real_t Mc[3][3];
+    for (int r = 0; r < 3; r++)
+      for (int s = 0; s < 3; s++) Mc[r][s] = (s == c) ? C[r] : M[r][s];
+    J[c] = det3(Mc) * inv;
+  }
+}
+
 /* B == NULL: the vertex fields are pulled back from B0 on the spot (sampled evaluation) */
 static void mimetic_current(const grid_t *g, const real_t *x, const real_t *B, const real_t *B0, const int p[3],
                             real_t J[3]) {
+  if (g_curl == 1) {
+    octilateral_current(g, x, B, B0, p, J);
+    return;
+  }
   const long N = g->N;
   real_t M[3][3], C[3];
   real_t xp[3];
@@ -559,6 +647,14 @@ int orc_ck_attempt(const int n[3], const double h[3], const int bc[3], double ga
 }
 
 /* OpenMP threads the sweeps use */
+/* current operator of the later calls: 0 nearest-neighbour loops (Sec. 2.2), 1 the
+ * next-nearest-neighbour octilateral (Sec. 2.3) */
+int orc_set_curl(int kind) {
+  if (kind != 0 && kind != 1) return ORC_E_ARG;
+  g_curl = kind;
+  return ORC_OK;
+}
+
 int orc_threads(void) { return omp_get_max_threads(); }
 
 /* Set the OpenMP threads of later sweeps (timing of the oracle on a given core count). */

@@ -672,3 +672,104 @@ def test_complex_step_matches_central_difference():
     fd = (energy(h) - energy(-h)) / (2 * h)
     assert E.real == pytest.approx(oracle.diagnostics(g, E_real["x"], B0)["E_M"], rel=1e-13)
     assert E.imag / eps == pytest.approx(fd, rel=1e-7)
+
+
+# --------------------------------------------------------------------------------------
+# T16: the next-nearest-neighbour (octilateral) current of Sec. 2.3
+# --------------------------------------------------------------------------------------
+def smoothed_central_curl(g, B):
+    """The curl that the octilateral loops reduce to on the undistorted grid: each derivative
+    is the central difference along its axis averaged over the three lines of the loop's
+    plane with weights 1/4, 1/2, 1/4 (the trapezoid rule along the edges of the 2h x 2h
+    square through the eight ring neighbours).  numpy.roll throughout; valid on interior
+    nodes."""
+    def roll(f, a, s):
+        return np.roll(f, s, axis=2 - a)
+
+    def D(f, a, b):  # d/dX_a, smoothed along axis b
+        sm = 0.25 * roll(f, b, 1) + 0.5 * f + 0.25 * roll(f, b, -1)
+        return (roll(sm, a, -1) - roll(sm, a, 1)) / (2 * g.h[a])
+    Bx, By, Bz = B
+    return np.stack([D(Bz, 1, 2) - D(By, 2, 1), D(Bx, 2, 0) - D(Bz, 0, 2), D(By, 0, 1) - D(Bx, 1, 0)])
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 0), (1, 0, 1), (1, 1, 1)])
+def test_T16_octilateral_undistorted_grid_gives_smoothed_central_curl(bc):
+    g = W.make_grid((9, 10, 11), [(-1.0, 1.4), (0.0, 2.25), (-2.0, 0.0)], bc)
+    B0 = W.smooth_random_field(g, 1.0, seed=11, mmax=3) + np.random.default_rng(3).normal(size=g.shape) * 0.3
+    with oracle.curl(oracle.CURL_NNN):
+        f = oracle.fields(g, g.identity(), B0)
+    s = (slice(None),) + interior(g)
+    assert nrel(f["J"][s], smoothed_central_curl(g, B0)[s]) < 1e-13
+    # and it is not the nearest-neighbour operator
+    assert nrel(f["J"][s], central_curl(g, B0)[s]) > 1e-3
+
+
+def _field_for_target(g, x, Bt):
+    """B0 whose pull-back on positions x is Bt: the oracle's own F columns from three uniform
+    fields (B = F e_a / det F), then B0 = det F F^-1 Bt node by node."""
+    cols = []
+    for a in range(3):
+        e = np.zeros(g.shape)
+        e[a] = 1.0
+        f = oracle.fields(g, x, e)
+        cols.append(f["B"] * f["det"])
+    F = np.stack(cols, axis=1)  # (3 rows, 3 cols, nz, ny, nx)
+    det = f["det"]
+    Fm = np.moveaxis(F, (0, 1), (-2, -1))
+    return np.moveaxis(np.linalg.solve(Fm, np.moveaxis(Bt, 0, -1)[..., None])[..., 0], -1, 0) * det
+
+
+@pytest.mark.parametrize("curl_kind", [0, 1])
+def test_T16_linear_field_on_distorted_grid_exact_curl(curl_kind):
+    """A field linear in x, B = M x + c, on a non-affine, smoothly distorted grid (loops that
+    are neither planar nor regular): the trapezoid circulation of a linear field along straight
+    edges is exact, and Stokes holds exactly for its constant curl over any closed polygon, so J
+    is the exact curl at every interior node if and only if the area vector is the loop's
+    vector area.  For the octilateral that pins the circulation, the eight surface elements
+    (the reading of dx_A..dx_D) and the solve; for the nearest-neighbour loops, the same."""
+    rng = np.random.default_rng(31)
+    M = rng.standard_normal((3, 3))
+    c = rng.standard_normal(3)
+    g = W.make_grid((9, 8, 10), [(-1.0, 1.0), (-0.8, 0.9), (-1.2, 1.0)], (0, 0, 0))
+    x = g.identity() + W.wall_sine_displacement(g, 0.06, seed=4, lo=-1.2, hi=1.2)
+    Bt = np.einsum("ij,j...->i...", M, x) + c[:, None, None, None]
+    B0 = _field_for_target(g, x, Bt)
+    with oracle.curl(curl_kind):
+        f = oracle.fields(g, x, B0)
+    assert nrel(f["B"], Bt) < 1e-13
+    curl = np.array([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]])
+    Ji = f["J"][(slice(None),) + interior(g)].reshape(3, -1)
+    assert np.abs(Ji - curl[:, None]).max() < 1e-11 * np.abs(curl).max()
+
+
+def test_T16_octilateral_second_order_and_close_to_nearest_neighbour():
+    """On a smooth field and a smooth distortion both operators approximate the curl to second
+    order: halving h cuts the octilateral's difference from the nearest-neighbour current by
+    about four."""
+    diffs = []
+    for n in (12, 24):
+        g = W.make_grid((n, n, n), [(0.0, 2 * np.pi)] * 3, (1, 1, 1))
+        x0 = g.identity() + 0.05 * np.stack([np.sin(g.coords()[1]), np.sin(g.coords()[2]), np.sin(g.coords()[0])])
+        B0 = W.abc_field(g)
+        a = oracle.fields(g, x0, B0)["J"]
+        with oracle.curl(oracle.CURL_NNN):
+            b = oracle.fields(g, x0, B0)["J"]
+        diffs.append(nrel(b, a))
+    assert 3.0 < diffs[0] / diffs[1] < 5.0, diffs
+
+
+def test_T16_octilateral_rigid_rotation_and_translation():
+    """Rotating the positions and B0's image rigidly rotates J (the loops are built from
+    differences of positions only)."""
+    g = W.make_grid((8, 9, 7), [(-1.0, 1.0), (-1.0, 1.2), (-0.7, 0.9)], (0, 0, 0))
+    x = g.identity() + W.wall_sine_displacement(g, 0.05, seed=8, lo=-1.0, hi=1.2)
+    B0 = W.smooth_random_field(g, 1.0, seed=9)
+    th = 0.7
+    Q = np.array([[np.cos(th), -np.sin(th), 0.0], [np.sin(th), np.cos(th), 0.0], [0.0, 0.0, 1.0]])
+    with oracle.curl(oracle.CURL_NNN):
+        f = oracle.fields(g, x, B0)
+        xr = np.einsum("ij,j...->i...", Q, x) + np.array([0.3, -1.0, 2.0])[:, None, None, None]
+        fr = oracle.fields(g, xr, B0)
+    assert nrel(fr["J"], np.einsum("ij,j...->i...", Q, f["J"])) < 1e-12
+    assert nrel(fr["B"], np.einsum("ij,j...->i...", Q, f["B"])) < 1e-13
