@@ -48,6 +48,7 @@ enum {
 
 enum { RELAX_LINE_TIED = 0, RELAX_PERIODIC = 1 };
 enum { RELAX_FP64 = 0, RELAX_FP32_MIXED = 1 };
+enum { RELAX_CURL_NN = 0, RELAX_CURL_NNN = 1 };
 
 typedef struct {
   int n[3];             /* nodes along x, y, z; each >= 4, n[0] * n[1] < 2^28 */
@@ -70,6 +71,10 @@ typedef struct {
                            stability-limited run near equilibrium, where Lambda barely depends
                            on dt, can retry a rejected step with nearly the same dt for a very
                            long time.  0.9 (the Numerical Recipes value) avoids that. */
+  int curl;             /* RELAX_CURL_NN: the current from loops over the four in-plane nearest
+                           neighbours (Sec. 2.2), the default; RELAX_CURL_NNN: loops over the
+                           octilateral of the eight in-plane ring neighbours (Sec. 2.3; FP64
+                           only, no relax_backward) */
 } relax_config;
 
 /* Per accepted step, evaluated at the state the step starts from (pre-step). */

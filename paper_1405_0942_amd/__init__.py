@@ -23,6 +23,7 @@ RELAX_OK, RELAX_E_ARG, RELAX_E_HIP, RELAX_E_FOLD, RELAX_E_DT, RELAX_E_NAN, RELAX
     0, -1, -2, -3, -4, -5, -6, -7)
 RELAX_LINE_TIED, RELAX_PERIODIC = 0, 1
 RELAX_FP64, RELAX_FP32_MIXED = 0, 1
+RELAX_CURL_NN, RELAX_CURL_NNN = 0, 1
 
 # every symbol include/relax.h declares
 EXPORTS = ("relax_workspace_bytes", "relax_init", "relax_step", "relax_diagnostics", "relax_diagnostics_noalloc",
@@ -50,7 +51,7 @@ class relax_config(C.Structure):
     _fields_ = [("n", C.c_int * 3), ("h", C.c_double * 3), ("bc", C.c_int * 3), ("precision", C.c_int),
                 ("gamma", C.c_double), ("dt0", C.c_double), ("dt_min", C.c_double), ("tol", C.c_double),
                 ("adaptive", C.c_int), ("record", C.c_int), ("checkpoint_every", C.c_int),
-                ("xi_null_tau", C.c_double), ("safety", C.c_double)]
+                ("xi_null_tau", C.c_double), ("safety", C.c_double), ("curl", C.c_int)]
 
 
 class relax_diag(C.Structure):
@@ -215,7 +216,7 @@ DIAG_FIELDS = ("t", "dt", "E_M", "xi", "R2", "Lambda", "min_det", "rejects", "co
 
 
 def make_config(grid, precision=RELAX_FP64, gamma=1.0, dt0=1e-3, dt_min=1e-12, tol=1e-7, adaptive=True,
-                record=False, checkpoint_every=20, xi_null_tau=1e-12, safety=1.0) -> relax_config:
+                record=False, checkpoint_every=20, xi_null_tau=1e-12, safety=1.0, curl=RELAX_CURL_NN) -> relax_config:
     """Build a relax_config from any grid with attributes n, h, bc."""
     c = relax_config()
     c.n[:] = [int(v) for v in grid.n]
@@ -231,6 +232,7 @@ def make_config(grid, precision=RELAX_FP64, gamma=1.0, dt0=1e-3, dt_min=1e-12, t
     c.checkpoint_every = int(checkpoint_every)
     c.xi_null_tau = float(xi_null_tau)
     c.safety = float(safety)
+    c.curl = int(curl)
     return c
 
 

@@ -113,6 +113,8 @@ bool valid_config(const relax_config* c) {
   if (c->adaptive != 0 && c->adaptive != 1) return false;
   if (c->record != 0 && c->record != 1) return false;
   if (c->record && c->checkpoint_every < 1) return false;
+  if (c->curl != RELAX_CURL_NN && c->curl != RELAX_CURL_NNN) return false;
+  if (c->curl == RELAX_CURL_NNN && c->precision != RELAX_FP64) return false;
   return true;
 }
 
@@ -163,6 +165,7 @@ Geometry make_geometry(const relax_config* c) {
   g.tz = choose_tz(c, g.tiles[0] * g.tiles[1]);
   g.tiles[2] = (c->n[2] + g.tz - 1) / g.tz;
   g.nblocks = g.tiles[0] * g.tiles[1] * g.tiles[2];
+  g.curl = c->curl;
   return g;
 }
 
@@ -548,6 +551,7 @@ int relax_backward(void* ctx, double seed_EM, double seed_R2, double* d_grad_x0,
   if (!c || !d_grad_x0 || !d_grad_B0 || !std::isfinite(seed_EM) || !std::isfinite(seed_R2)) return RELAX_E_ARG;
   if (c->status != RELAX_OK) return RELAX_E_STATE;
   if (c->mixed) return fail(c, RELAX_E_ARG, "relax_backward: needs an FP64 context");
+  if (c->cfg.curl != RELAX_CURL_NN) return fail(c, RELAX_E_ARG, "relax_backward: nearest-neighbour current only");
   if (c->L.ckpt_slots == 0) return fail(c, RELAX_E_STATE, "relax_backward: context created without record");
   if (seed_R2 != 0.0 && c->cfg.gamma == 0.0) return fail(c, RELAX_E_ARG, "relax_backward: R2 seed needs gamma != 0");
   int rc = sync_ctl(c);

@@ -27,6 +27,7 @@ constexpr int NPART = 8;                   // doubles per workgroup partial reco
 constexpr int RING_CAP = 4096;             // per-call diagnostics ring entries
 
 enum { BC_LINE_TIED = 0, BC_PERIODIC = 1 };
+enum { CURL_NN = 0, CURL_NNN = 1 };  // the values of RELAX_CURL_NN / RELAX_CURL_NNN
 
 struct Geometry {
   int n[3];          // nodes along x, y, z
@@ -40,6 +41,8 @@ struct Geometry {
   int tiles[3];      // tiles along x, along y, z-chunks
   int tz;            // z-chunk length
   int nblocks;       // tiles[0] * tiles[1] * tiles[2]
+  int curl;          // CURL_NN: loops over the four nearest neighbours (Sec. 2.2); CURL_NNN:
+                     // the octilateral over the eight ring neighbours (Sec. 2.3)
 };
 
 // Device-resident step state.  Written only by the control kernel (and by small set-up

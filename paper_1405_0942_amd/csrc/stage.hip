@@ -86,9 +86,16 @@ __device__ __forceinline__ double wave_min(double v) {
 // diagnostics sweep of x[diag_buf]: no step gating and no k_1; writes u (optionally scaled by
 // det F), B, J, alpha* and the convexity where the caller asked for them.  REC (FP64 stages
 // 4 and 6): also store the stage input at the node, for the reverse sweeps.
-template <int S, bool MIXED, bool XYP, bool DIAG = false, bool REC = false>
+template <int S, bool MIXED, bool XYP, bool DIAG = false, bool REC = false, bool NNN = false>
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) void stage_kernel(SweepArgs a) {
   using T = typename std::conditional<MIXED, float, double>::type;
+  // NNN: the current from the next-nearest-neighbour octilateral loops (Sec. 2.3), which reach
+  // positions and B on the planes q - 1 and q + 1 with an x-y offset: the stage-input ring
+  // keeps five planes and the B ring three
+  constexpr int RYS = NNN ? 5 : 3;
+  constexpr int RBS = NNN ? 3 : 2;
+  auto yslot = [](int p) { return (int)((unsigned)(p + 1024 * RYS) % (unsigned)RYS); };
+  auto bslot = [](int p) { return (int)((unsigned)(p + 1024 * RBS) % (unsigned)RBS); };
   constexpr bool STAGE1 = (S == 1);
   constexpr bool LAST = (S == 6);
   // the window is a base vector (x_n; y_3 in stage 3, y_5 in stage 5) plus at most one vector
@@ -106,6 +113,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   constexpr int NP1 = (RY1 * RX1 + NTHREADS - 1) / NTHREADS;  // field points per thread
   static_assert(!DIAG || (S == 1 && !MIXED), "the diagnostics sweep is the FP64 stage-1 sweep");
   static_assert(!REC || (!MIXED && (S == 4 || S == 6)), "REC: FP64 stages 4 and 6");
+  static_assert(!NNN || (!MIXED && !REC), "the octilateral current is an FP64 forward operator");
 
   Control* ctl = a.ctl;
   constexpr bool diag_only = DIAG;
@@ -152,8 +160,8 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
 
-  __shared__ double ys[3][3][RY2 * RX2];  // stage input, tile + 2-node halo, ring of 3 planes
-  __shared__ T bs[2][3][RY1 * RX1];       // pulled-back field, tile + 1-node halo, 2 planes
+  __shared__ double ys[RYS][3][RY2 * RX2];  // stage input, tile + 2-node halo, ring of planes
+  __shared__ T bs[RBS][3][RY1 * RX1];       // pulled-back field, tile + 1-node halo, ring of planes
   __shared__ double red[NTHREADS / 64][NPART];
 
   const double* __restrict__ xn = a.x[cur];
@@ -269,7 +277,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   // y = base + cv v, rounded once, plus the periodic shift of a wrapped neighbour
   auto commit_window = [&](int pz) {
     const AxisIdx rz = resolve_near(pz, nz, bcz);
-    const int slot = mod3(pz);
+    const int slot = yslot(pz);
     const double shz = rz.w * g.period[2];
 #pragma unroll
     for (int r = 0; r < NP2; r++) {
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   // ---- unscaled Jacobian at a window point (r, c in stage-input window coordinates) -----
   auto jac_xy = [&](int r, int c, int p, int gi, int gj, double F[3][3]) {
     const int o = r * RX2 + c;
-    const int sp = mod3(p);
+    const int sp = yslot(p);
 #pragma unroll
     for (int m = 0; m < 3; m++) {
       const double* yc = ys[sp][m];
@@ -362,14 +370,14 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     jac_xy(r, c, p, gi, gj, F);
     const int o = r * RX2 + c;
     if (bcz == BC_PERIODIC || (p > 0 && p < nz - 1)) {
-      const int sa = mod3(p + 1), sb = mod3(p - 1);
+      const int sa = yslot(p + 1), sb = yslot(p - 1);
 #pragma unroll
       for (int m = 0; m < 3; m++) F[m][2] = ys[sa][m][o] - ys[sb][m][o];
     } else if (p == 0) {
 #pragma unroll
-      for (int m = 0; m < 3; m++) F[m][2] = -3.0 * ys[0][m][o] + 4.0 * ys[1][m][o] - ys[2][m][o];
+      for (int m = 0; m < 3; m++) F[m][2] = -3.0 * ys[yslot(0)][m][o] + 4.0 * ys[yslot(1)][m][o] - ys[yslot(2)][m][o];
     } else {
-      const int s0 = mod3(p), s1 = mod3(p - 1), s2 = mod3(p - 2);
+      const int s0 = yslot(p), s1 = yslot(p - 1), s2 = yslot(p - 2);
 #pragma unroll
       for (int m = 0; m < 3; m++) F[m][2] = 3.0 * ys[s0][m][o] - 4.0 * ys[s1][m][o] + ys[s2][m][o];
     }
@@ -497,7 +505,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     double Dp = 0.0;
     int kap_p = 1;
     if (p <= pb1) {
-      const int sb = p & 1;
+      const int sb = bslot(p);
 #pragma unroll
       for (int r = 0; r < NP1; r++) {
         __builtin_amdgcn_sched_barrier(0);  // one field point at a time: bounds live temporaries
@@ -549,7 +557,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                   // convexity (Sec. 3.2.3, eq. "convexity"): every trihedron of edge vectors to
                   // the neighbours p + di e_x, p + dj e_y, p + dk e_z must have a determinant of
                   // sign di dj dk; trihedra beyond a line-tied face are not formed
-                  const int oc = (r1 + 1) * RX2 + (c1 + 1), sc = mod3(p);
+                  const int oc = (r1 + 1) * RX2 + (c1 + 1), sc = yslot(p);
                   const bool lox = XYP || bcx == BC_PERIODIC || gi > 0, hix = XYP || bcx == BC_PERIODIC || gi < nx - 1;
                   const bool loy = XYP || bcy == BC_PERIODIC || gj > 0, hiy = XYP || bcy == BC_PERIODIC || gj < ny - 1;
                   const bool loz = bcz == BC_PERIODIC || p > 0, hiz = bcz == BC_PERIODIC || p < nz - 1;
@@ -561,8 +569,8 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
                     ex[1][m] = ys[sc][m][oc + 1] - c0;
                     ey[0][m] = ys[sc][m][oc - RX2] - c0;
                     ey[1][m] = ys[sc][m][oc + RX2] - c0;
-                    ez[0][m] = loz ? ys[mod3(p - 1)][m][oc] - c0 : 0.0;
-                    ez[1][m] = hiz ? ys[mod3(p + 1)][m][oc] - c0 : 0.0;
+                    ez[0][m] = loz ? ys[yslot(p - 1)][m][oc] - c0 : 0.0;
+                    ez[1][m] = hiz ? ys[yslot(p + 1)][m][oc] - c0 : 0.0;
                   }
                   bool convex = true;
 #pragma unroll
@@ -595,7 +603,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
     if (qout) {
       double Ft[3][3];
       jac_xy(ty + 2, tx + 2, q, gi_t, gj_t, Ft);
-      const int o = (ty + 2) * RX2 + tx + 2, sq = mod3(q);
+      const int o = (ty + 2) * RX2 + tx + 2, sq = yslot(q);
 #pragma unroll
       for (int m = 0; m < 3; m++) {
         Fxy[m][0] = (T)Ft[m][0];
@@ -639,32 +647,138 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       }
       if (!face) {
         const int o = (ty + 1) * RX1 + (tx + 1);
-        const int sq = q & 1;
-        T G[3][3];  // G'[a][m] = B_m(n + e_a) - B_m(n - e_a)
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-          G[0][m] = bs[sq][m][o + 1] - bs[sq][m][o - 1];
-          G[1][m] = bs[sq][m][o + RX1] - bs[sq][m][o - RX1];
-          G[2][m] = Bp[m] - Bqm[m];
-        }
-        T Fq[3][3];
-#pragma unroll
-        for (int m = 0; m < 3; m++) {
-          Fq[m][0] = Fxy[m][0];
-          Fq[m][1] = Fxy[m][1];
-          Fq[m][2] = Fzq[m];
-        }
-        // c'_q = (F' e_b) . G'_a - (F' e_a) . G'_b, (a, b, q) = (y, z, x), (z, x, y), (x, y, z)
-        T cq[3];
-        cq[0] = Fq[0][2] * G[1][0] + Fq[1][2] * G[1][1] + Fq[2][2] * G[1][2] -
-                (Fq[0][1] * G[2][0] + Fq[1][1] * G[2][1] + Fq[2][1] * G[2][2]);
-        cq[1] = Fq[0][0] * G[2][0] + Fq[1][0] * G[2][1] + Fq[2][0] * G[2][2] -
-                (Fq[0][2] * G[0][0] + Fq[1][2] * G[0][1] + Fq[2][2] * G[0][2]);
-        cq[2] = Fq[0][1] * G[0][0] + Fq[1][1] * G[0][1] + Fq[2][1] * G[0][2] -
-                (Fq[0][0] * G[1][0] + Fq[1][0] * G[1][1] + Fq[2][0] * G[1][2]);
+        const int sq = bslot(q);
         T J[3];
+        if constexpr (NNN) {
+          // the octilateral loops of Sec. 2.3 through the eight ring neighbours of each grid
+          // plane, taken literally: vertices V1..V8 = +a, +a+b, +b, -a+b, -a, -a-b, -b, +a-b;
+          // circulation sum (B_r + B_r+1)/2 . dx_r; area vector = the triangles at the edge
+          // points (V2 V3 V4, V4 V5 V6, V6 V7 V8, V8 V1 V2) plus the quadrilateral through the
+          // diagonal points V2 V4 V6 V8; then J . N_q = C_q by Cramer's rule
+          const int oy = (ty + 2) * RX2 + tx + 2;
+          constexpr int RD[9][2] = {{1, 0}, {1, 1}, {0, 1}, {-1, 1}, {-1, 0}, {-1, -1}, {0, -1}, {1, -1}, {1, 0}};
+          double Mq[3][3], Cq[3];
+#pragma unroll 1
+          for (int qa = 0; qa < 3; qa++) {
+            // (a, b) = (y, z), (z, x), (x, y); walk V1..V8 and back to V1, keeping only the
+            // previous vertex, the previous edge and the diagonal points met so far
+            double Vp[3], Bvp[3], ep[3], e1[3], D1[3], Dp[3], q1[3], qp[3];
+            double circ = 0.0, nA[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int m = 0; m < 3; m++) J[m] = (Fq[m][0] * cq[0] + Fq[m][1] * cq[1] + Fq[m][2] * cq[2]) * rDq;
+            for (int r = 0; r <= 8; r++) {
+              const int da = RD[r][0], db = RD[r][1];
+              const int dx = qa == 2 ? da : (qa == 1 ? db : 0);
+              const int dy = qa == 0 ? da : (qa == 2 ? db : 0);
+              const int dz = qa == 0 ? db : (qa == 1 ? da : 0);
+              const int sy = yslot(q + dz), sbv = bslot(q + dz);
+              double V[3], Bv[3];
+#pragma unroll
+              for (int m = 0; m < 3; m++) {
+                V[m] = ys[sy][m][oy + dy * RX2 + dx];
+                Bv[m] = (double)bs[sbv][m][o + dy * RX1 + dx];
+              }
+              if (r > 0) {
+                double e[3];
+#pragma unroll
+                for (int m = 0; m < 3; m++) {
+                  e[m] = V[m] - Vp[m];  // dx_r (1-based r), from V_r to V_r+1
+                  circ += 0.5 * (Bvp[m] + Bv[m]) * e[m];
+                }
+                // triangles at the edge points: dx2 x dx3, dx4 x dx5, dx6 x dx7 and dx8 x dx1
+                if (r == 3 || r == 5 || r == 7) {
+                  nA[0] += 0.5 * (ep[1] * e[2] - ep[2] * e[1]);
+                  nA[1] += 0.5 * (ep[2] * e[0] - ep[0] * e[2]);
+                  nA[2] += 0.5 * (ep[0] * e[1] - ep[1] * e[0]);
+                }
+                if (r == 8) {
+                  nA[0] += 0.5 * (e[1] * e1[2] - e[2] * e1[1]);
+                  nA[1] += 0.5 * (e[2] * e1[0] - e[0] * e1[2]);
+                  nA[2] += 0.5 * (e[0] * e1[1] - e[1] * e1[0]);
+                }
+#pragma unroll
+                for (int m = 0; m < 3; m++) {
+                  if (r == 1) e1[m] = e[m];
+                  ep[m] = e[m];
+                }
+              }
+              // the quadrilateral through the diagonal points V2, V4, V6, V8 (r = 1, 3, 5, 7):
+              // edges dx_A..dx_D and the sum of their consecutive cross products over 4
+              if (r == 1 || r == 3 || r == 5 || r == 7) {
+                if (r == 1) {
+#pragma unroll
+                  for (int m = 0; m < 3; m++) D1[m] = V[m];
+                } else {
+                  double qe[3];
+#pragma unroll
+                  for (int m = 0; m < 3; m++) qe[m] = V[m] - Dp[m];
+                  if (r == 3) {
+#pragma unroll
+                    for (int m = 0; m < 3; m++) q1[m] = qe[m];
+                  } else {
+                    nA[0] += 0.25 * (qp[1] * qe[2] - qp[2] * qe[1]);
+                    nA[1] += 0.25 * (qp[2] * qe[0] - qp[0] * qe[2]);
+                    nA[2] += 0.25 * (qp[0] * qe[1] - qp[1] * qe[0]);
+                  }
+#pragma unroll
+                  for (int m = 0; m < 3; m++) qp[m] = qe[m];
+                  if (r == 7) {  // the closing edge V8 -> V2, then its products with dx_C and dx_A
+                    double qd[3];
+#pragma unroll
+                    for (int m = 0; m < 3; m++) qd[m] = D1[m] - V[m];
+                    nA[0] += 0.25 * (qe[1] * qd[2] - qe[2] * qd[1]) + 0.25 * (qd[1] * q1[2] - qd[2] * q1[1]);
+                    nA[1] += 0.25 * (qe[2] * qd[0] - qe[0] * qd[2]) + 0.25 * (qd[2] * q1[0] - qd[0] * q1[2]);
+                    nA[2] += 0.25 * (qe[0] * qd[1] - qe[1] * qd[0]) + 0.25 * (qd[0] * q1[1] - qd[1] * q1[0]);
+                  }
+                }
+#pragma unroll
+                for (int m = 0; m < 3; m++) Dp[m] = V[m];
+              }
+#pragma unroll
+              for (int m = 0; m < 3; m++) {
+                Vp[m] = V[m];
+                Bvp[m] = Bv[m];
+              }
+            }
+#pragma unroll
+            for (int m = 0; m < 3; m++) Mq[qa][m] = nA[m];
+            Cq[qa] = circ;
+          }
+          const double iM = 1.0 / det3(Mq);
+#pragma unroll
+          for (int c = 0; c < 3; c++) {
+            double Mc[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; r++)
+#pragma unroll
+              for (int k = 0; k < 3; k++) Mc[r][k] = (k == c) ? Cq[r] : Mq[r][k];
+            J[c] = (T)(det3(Mc) * iM);
+          }
+        } else {
+          T G[3][3];  // G'[a][m] = B_m(n + e_a) - B_m(n - e_a)
+#pragma unroll
+          for (int m = 0; m < 3; m++) {
+            G[0][m] = bs[sq][m][o + 1] - bs[sq][m][o - 1];
+            G[1][m] = bs[sq][m][o + RX1] - bs[sq][m][o - RX1];
+            G[2][m] = Bp[m] - Bqm[m];
+          }
+          T Fq[3][3];
+#pragma unroll
+          for (int m = 0; m < 3; m++) {
+            Fq[m][0] = Fxy[m][0];
+            Fq[m][1] = Fxy[m][1];
+            Fq[m][2] = Fzq[m];
+          }
+          // c'_q = (F' e_b) . G'_a - (F' e_a) . G'_b, (a, b, q) = (y, z, x), (z, x, y), (x, y, z)
+          T cq[3];
+          cq[0] = Fq[0][2] * G[1][0] + Fq[1][2] * G[1][1] + Fq[2][2] * G[1][2] -
+                  (Fq[0][1] * G[2][0] + Fq[1][1] * G[2][1] + Fq[2][1] * G[2][2]);
+          cq[1] = Fq[0][0] * G[2][0] + Fq[1][0] * G[2][1] + Fq[2][0] * G[2][2] -
+                  (Fq[0][2] * G[0][0] + Fq[1][2] * G[0][1] + Fq[2][2] * G[0][2]);
+          cq[2] = Fq[0][1] * G[0][0] + Fq[1][1] * G[0][1] + Fq[2][1] * G[0][2] -
+                  (Fq[0][0] * G[1][0] + Fq[1][0] * G[1][1] + Fq[2][0] * G[1][2]);
+#pragma unroll
+          for (int m = 0; m < 3; m++) J[m] = (Fq[m][0] * cq[0] + Fq[m][1] * cq[1] + Fq[m][2] * cq[2]) * rDq;
+        }
         if constexpr (DIAG) {
 #pragma unroll
           for (int m = 0; m < 3; m++) so_p[1][m] = J[m];
@@ -824,16 +938,16 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   }
 }
 
-template <bool MIXED, bool XYP>
+template <bool MIXED, bool XYP, bool NNN = false>
 hipError_t launch_stage_t(int s, const SweepArgs& a, hipStream_t st) {
   const dim3 grid(a.g.nblocks), block(NTHREADS);
   switch (s) {
-    case 1: hipLaunchKernelGGL((stage_kernel<1, MIXED, XYP>), grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL((stage_kernel<2, MIXED, XYP>), grid, block, 0, st, a); break;
-    case 3: hipLaunchKernelGGL((stage_kernel<3, MIXED, XYP>), grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL((stage_kernel<4, MIXED, XYP>), grid, block, 0, st, a); break;
-    case 5: hipLaunchKernelGGL((stage_kernel<5, MIXED, XYP>), grid, block, 0, st, a); break;
-    case 6: hipLaunchKernelGGL((stage_kernel<6, MIXED, XYP>), grid, block, 0, st, a); break;
+    case 1: hipLaunchKernelGGL((stage_kernel<1, MIXED, XYP, false, false, NNN>), grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL((stage_kernel<2, MIXED, XYP, false, false, NNN>), grid, block, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((stage_kernel<3, MIXED, XYP, false, false, NNN>), grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((stage_kernel<4, MIXED, XYP, false, false, NNN>), grid, block, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((stage_kernel<5, MIXED, XYP, false, false, NNN>), grid, block, 0, st, a); break;
+    case 6: hipLaunchKernelGGL((stage_kernel<6, MIXED, XYP, false, false, NNN>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -851,26 +965,35 @@ hipError_t launch_stage_rec_t(int s, const SweepArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <bool XYP, bool NNN>
+hipError_t launch_diagnostics_t(const SweepArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((stage_kernel<1, false, XYP, true, false, NNN>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_stage(int s, bool mixed, const SweepArgs& a, hipStream_t st) {
   const bool xyp = (a.g.bc[0] == BC_PERIODIC && a.g.bc[1] == BC_PERIODIC);
+  if (a.g.curl == CURL_NNN) {
+    if (mixed) return hipErrorInvalidValue;
+    return xyp ? launch_stage_t<false, true, true>(s, a, st) : launch_stage_t<false, false, true>(s, a, st);
+  }
   if (mixed) return xyp ? launch_stage_t<true, true>(s, a, st) : launch_stage_t<true, false>(s, a, st);
   return xyp ? launch_stage_t<false, true>(s, a, st) : launch_stage_t<false, false>(s, a, st);
 }
 
 hipError_t launch_stage_rec(int s, const SweepArgs& a, hipStream_t st) {
+  if (a.g.curl == CURL_NNN) return hipErrorInvalidValue;
   const bool xyp = (a.g.bc[0] == BC_PERIODIC && a.g.bc[1] == BC_PERIODIC);
   return xyp ? launch_stage_rec_t<true>(s, a, st) : launch_stage_rec_t<false>(s, a, st);
 }
 
 hipError_t launch_diagnostics(const SweepArgs& a, hipStream_t st) {
   const bool xyp = (a.g.bc[0] == BC_PERIODIC && a.g.bc[1] == BC_PERIODIC);
-  if (xyp)
-    hipLaunchKernelGGL((stage_kernel<1, false, true, true>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
-  else
-    hipLaunchKernelGGL((stage_kernel<1, false, false, true>), dim3(a.g.nblocks), dim3(NTHREADS), 0, st, a);
-  return hipGetLastError();
+  if (a.g.curl == CURL_NNN)
+    return xyp ? launch_diagnostics_t<true, true>(a, st) : launch_diagnostics_t<false, true>(a, st);
+  return xyp ? launch_diagnostics_t<true, false>(a, st) : launch_diagnostics_t<false, false>(a, st);
 }
 
 }  // namespace relax

@@ -110,8 +110,8 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu():
 
 def test_config_struct_layout_matches_header():
     # n[3] int, h[3] double, bc[3] int, precision int, gamma, dt0, dt_min, tol double,
-    # adaptive, record, checkpoint_every int, xi_null_tau double
-    assert ctypes.sizeof(R.relax_config) == 12 + 4 + 24 + 12 + 4 + 32 + 12 + 4 + 8 + 8
+    # adaptive, record, checkpoint_every int, xi_null_tau double, safety double, curl int (+4 pad)
+    assert ctypes.sizeof(R.relax_config) == 12 + 4 + 24 + 12 + 4 + 32 + 12 + 4 + 8 + 8 + 4 + 4
     assert ctypes.sizeof(R.relax_diag) == 7 * 8 + 8
 
 
