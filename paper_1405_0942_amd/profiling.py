@@ -55,7 +55,8 @@ def read_counter(run_dir: str, counter: str):
 
 
 def _stage_of(name: str):
-    m = re.search(r"stage_kernel<(\d), (false|true), (false|true)(?:, false(?:, (?:false|true))?)?>", name)
+    # stage_kernel<S, MIXED, XYP[, DIAG[, REC[, NNN]]]>; the diagnostics variant (DIAG true) is not a stage
+    m = re.search(r"stage_kernel<(\d), (false|true), (false|true)(?:, false(?:, (?:false|true)){0,2})?>", name)
     if not m:
         return None
     return int(m.group(1)), m.group(2) == "true"
