@@ -1,7 +1,7 @@
 // relax.cpp -- C ABI of the relaxation library (include/relax.h): configuration checks,
 // workspace carving, the launch sequence of a Cash-Karp step and the host side of the
 // device step controller.
-#include "../../include/relax.h"
+#include "relax.h"
 
 #include <hip/hip_runtime.h>
 

@@ -4,7 +4,7 @@
 // bandwidth ceiling that the sweeps are compared with; nothing on the relaxation path uses it.
 #include <hip/hip_runtime.h>
 
-#include "../../include/relax.h"
+#include "relax.h"
 
 namespace {
 
