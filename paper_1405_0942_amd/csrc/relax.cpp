@@ -24,6 +24,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+constexpr size_t STAGGER = 65536 + ALIGN;
 
 struct Layout {
   size_t ctl, x0, x1, k[3], y3, d4, y5, sum[3], B0, B0_64, part, lam, ring, out, dtrec, ckpt, total;
@@ -178,9 +179,12 @@ Layout make_layout(const relax_config* c, const Geometry& g, int K_record) {
   const size_t N3 = 3 * (size_t)g.N;
   const size_t ts = (c->precision == RELAX_FP32_MIXED) ? sizeof(float) : sizeof(double);
   size_t off = 0;
+  // consecutive arrays start STAGGER bytes further apart than their sizes: on power-of-two
+  // grids the arrays would otherwise be exact multiples of 2^k bytes apart, and the same node
+  // of every array the sweeps stream at once would fall on the same memory channel
   auto take = [&](size_t bytes) {
     size_t o = off;
-    off += align_up(bytes);
+    off += align_up(bytes) + STAGGER;
     return o;
   };
   L.ctl = take(sizeof(Control));

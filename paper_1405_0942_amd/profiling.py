@@ -24,7 +24,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/stage.hip", "csrc/sweep_common.h", "csrc/relax_device.h")
+KERNEL_SOURCES = ("csrc/stage.hip", "csrc/sweep_common.h", "csrc/relax_device.h", "csrc/relax.cpp")
 COPY_BYTES = 1 << 30
 
 
@@ -166,8 +166,39 @@ def main(argv=None):
     q.add_argument("--precision", choices=["fp64", "fp32-mixed"], default="fp64")
     q.add_argument("--nodes", type=int, required=True, help="grid nodes (counts are per 64 nodes)")
     q.add_argument("--command", required=True, help="the profiled commands, recorded in the summary")
+    m = sub.add_parser("pipe")
+    m.add_argument("--run", action="append", required=True, help="rocprofv3 output directory of a --pmc run")
+    m.add_argument("--workload", required=True)
+    m.add_argument("--precision", choices=["fp64", "fp32-mixed"], default="fp64")
+    m.add_argument("--nodes", type=int, required=True, help="grid nodes (counts are per 64 nodes)")
+    m.add_argument("--cus", type=int, default=256, help="compute units (one TA, TD and TCP each)")
+    m.add_argument("--xcds", type=int, default=8, help="XCDs (GRBM_GUI_ACTIVE is their sum)")
+    m.add_argument("--command", required=True, help="the profiled commands, recorded in the summary")
     args = ap.parse_args(argv)
     w = sys.stdout.write
+    if args.cmd == "pipe":
+        per = sq_counters(args.run, args.precision == "fp32-mixed")
+        w(f"# Vector-memory pipe of the stage sweeps, {args.workload}, {args.precision}\n\n")
+        w("Commands (from the repository root):\n\n")
+        w(f"    {args.command}\n\n")
+        w(f"Median over launches. Busy and stall columns: % of the launch's cycles (GRBM_GUI_ACTIVE / "
+          f"{args.xcds} XCDs), per unit (summed counter / {args.cus} CUs). Count columns: per 64 grid "
+          f"nodes (one wave's plane); SQ_WAIT_INST_LDS and SQ_ACTIVE_INST_LDS in units of 4 cycles.\n\n")
+        w(f"source_sha256: {kernel_source_hash()}\n\n")
+        busy = ["TA_TA_BUSY", "TD_TD_BUSY", "TCP_PENDING_STALL_CYCLES"]
+        counts = ["TA_BUFFER_READ_WAVEFRONTS", "TA_BUFFER_WRITE_WAVEFRONTS", "TCP_TCC_READ_REQ",
+                  "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS"]
+        cols = [c for c in busy + counts if any(c in v for v in per.values())]
+        w("| stage | " + " | ".join(cols) + " |\n|---|" + "---:|" * len(cols) + "\n")
+        batches = args.nodes / 64.0
+        for s_, v in per.items():
+            cyc = v.get("GRBM_GUI_ACTIVE", float("nan")) / args.xcds
+            cells = []
+            for c in cols:
+                x = v.get(c, float("nan"))
+                cells.append(f"{100.0 * x / args.cus / cyc:.0f} %" if c in busy else f"{x / batches:.1f}")
+            w(f"| {s_} | " + " | ".join(cells) + " |\n")
+        return
     if args.cmd == "sq":
         per = sq_counters(args.run, args.precision == "fp32-mixed")
         cols = sorted({c for v in per.values() for c in v})
