@@ -6,7 +6,7 @@ positions x0 = X + a seeded divergence-free Fourier displacement (|k| <= 3, max 
 A step is one accepted adaptive Cash-Karp RK5(4) step (six fused stage sweeps plus the
 device step control; rejected attempts are redone inside and counted in the time).
 
-    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed|both]
+    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed|both] [--curl nn|nnn]
 
 Prints one JSON line.  value = N * accepted steps / wall time of the timed relax_step
 call (inputs resident in HBM), FP64.  The FP32-mixed figures are in "fp32_mixed".
@@ -15,6 +15,8 @@ compulsory traffic per node, 72..192 B FP64 / 48..120 B FP32-mixed, times the no
 average launch duration (HIP events around each launch on the library's stream), against the
 8 TB/s HBM3E peak; config.step_hbm_frac is the same for the whole step (792 / 480 B per node
 per accepted step over the wall time per step, rejected attempts included in the time).
+--curl nnn times the same step with the octilateral current of Sec. 2.3 (FP64 only; no
+reverse-mode leg, which needs the nearest-neighbour current).
 """
 from __future__ import annotations
 
@@ -58,12 +60,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
-    cfg = R.make_config(w.grid, precision=precision, dt0=dt0, tol=tol, adaptive=True)
+def run_precision(R, torch, w, precision, steps, warmup, tol, dt0, curl=0):
+    cfg = R.make_config(w.grid, precision=precision, dt0=dt0, tol=tol, adaptive=True, curl=curl)
     x0 = torch.from_numpy(w.x0).cuda()
     B0 = torch.from_numpy(w.B0).cuda()
     N = w.grid.N
-    tag = "fp64" if precision == R.RELAX_FP64 else "fp32-mixed"
+    tag = ("fp64" if precision == R.RELAX_FP64 else "fp32-mixed") + ("-octilateral" if curl else "")
     out = {}
     with R.Relaxation(cfg, x0, B0) as r:
         del x0, B0
@@ -108,6 +110,7 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
     # whole step: the algorithmic bytes of one accepted step (rejected attempts are overhead)
     # over the wall time per accepted step; and what the design moves, rejected attempts included
     step_ms = wall * 1e3 / steps
+    step_tag = "fp64" if precision == R.RELAX_FP64 else "fp32-mixed"
     design_bytes = sum(design[s - 1] * (prof[f"stage{s}"][1] if s > 1 else steps) for s in range(1, 7)) / steps * N
     out.update(
         value=N * steps / wall,
@@ -119,7 +122,7 @@ def run_precision(R, torch, w, precision, steps, warmup, tol, dt0):
         xi_last=diag[-1]["xi"],
         E_first=diag[0]["E_M"],
         E_last=diag[-1]["E_M"],
-        step_algorithmic_GBs=ALGO_STEP[tag] * N / (step_ms * 1e-3) / 1e9,
+        step_algorithmic_GBs=ALGO_STEP[step_tag] * N / (step_ms * 1e-3) / 1e9,
         step_design_GBs=design_bytes / (step_ms * 1e-3) / 1e9,
         kernels=kernels,
         roofline={"bound": "hbm", "kernel": f"stage_kernel<{stage}> ({tag})",
@@ -286,7 +289,12 @@ def main():
                     help="fixed-dt steps of the FP32-mixed vs FP64 comparison at identical t")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the reverse-mode cost figure")
+    ap.add_argument("--curl", choices=["nn", "nnn"], default="nn",
+                    help="nearest-neighbour loops (Sec. 2.2) or the octilateral current (Sec. 2.3, FP64 only)")
     args = ap.parse_args()
+    if args.curl == "nnn" and args.precision != "fp64":
+        print("bench.py --curl nnn: the octilateral current is FP64 only; timing FP64", file=sys.stderr)
+        args.precision = "fp64"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the relaxation step has no multi-GPU path in this build "
@@ -307,8 +315,9 @@ def main():
     log(f"building inputs abc_{args.n}^3")
     w = W.abc_box(args.n)
     res = {}
+    curl = R.RELAX_CURL_NNN if args.curl == "nnn" else R.RELAX_CURL_NN
     if args.precision in ("fp64", "both"):
-        res["fp64"] = run_precision(R, torch, w, R.RELAX_FP64, args.steps, args.warmup, args.tol, args.dt0)
+        res["fp64"] = run_precision(R, torch, w, R.RELAX_FP64, args.steps, args.warmup, args.tol, args.dt0, curl)
     if args.precision in ("mixed", "both"):
         res["mixed"] = run_precision(R, torch, w, R.RELAX_FP32_MIXED, args.steps, args.warmup, args.tol, args.dt0)
     main_key = "fp64" if "fp64" in res else "mixed"
@@ -331,6 +340,8 @@ def main():
         "config": {"workload": f"{w.name}: ABC field A=B=C=1 on the periodic box [0,2pi)^3, x0 = X + "
                                f"divergence-free |k|<=3 displacement (max 0.1, seed 5)",
                    "grid": list(w.grid.n), "step": "one accepted adaptive Cash-Karp RK5(4) step",
+                   "current": ("octilateral loops over the eight ring neighbours (Sec. 2.3)" if args.curl == "nnn"
+                               else "loops over the four nearest neighbours (Sec. 2.2)"),
                    "tol": args.tol, "rejects_in_timed_steps": m["rejects"],
                    "step_algorithmic_bytes_per_node": ALGO_STEP[tag],
                    "step_hbm_GBs_algorithmic": m["step_algorithmic_GBs"],
@@ -353,13 +364,15 @@ def main():
                               "step_hbm_frac": mm["step_algorithmic_GBs"] / HBM_PEAK_GBS,
                               "step_hbm_GBs_design": mm["step_design_GBs"], "kernels": mm["kernels"],
                               "accuracy_vs_fp64_fixed_dt": acc}
-    if not args.no_adjoint:
+    if not args.no_adjoint and args.curl == "nn":
         log("adjoint cost: braid 64x64x192, 200 steps, checkpoints every 20")
         line["adjoint"] = adjoint_cost(R, torch, W)
     if not args.no_cpu_baseline:
         # fixed steps of the size the adaptive GPU run settled to (dt0 itself is above the
         # explicit stability limit of the 256^3 grid)
-        line["cpu_baseline"] = cpu_baseline(W, w, m["dt_last"], steps=args.cpu_steps)
+        import oracle
+        with oracle.curl(oracle.CURL_NNN if args.curl == "nnn" else oracle.CURL_NN):
+            line["cpu_baseline"] = cpu_baseline(W, w, m["dt_last"], steps=args.cpu_steps)
     print(json.dumps(line), flush=True)
 
 
