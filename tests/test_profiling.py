@@ -69,3 +69,28 @@ def test_read_traffic_parses_committed_summaries():
         for s in range(1, 7):
             assert float(rec[f"stage{s}_bytes_per_node"]) > 0
     assert P.read_traffic(os.path.join(root, "profiles", "no_such_file.txt")) is None
+
+
+def test_pipe_summary_normalises_busy_counters_and_counts(tmp_path, capsys):
+    name = "void relax::(anonymous namespace)::stage_kernel<3, false, true, false, false, false>(relax::SweepArgs)"
+    nodes = 64 * 1000
+    rows = [(1, name, "GRBM_GUI_ACTIVE", 8 * 1000.0),   # 1000 cycles per XCD
+            (1, name, "TA_TA_BUSY", 256 * 750.0),       # every TA busy 750 of them
+            (1, name, "TCP_TCC_READ_REQ", 76.0 * 1000)]  # 76 requests per 64 nodes
+    write_run(tmp_path / "p", rows)
+    P.main(["pipe", "--run", str(tmp_path / "p"), "--workload", "w", "--precision", "fp64",
+            "--nodes", str(nodes), "--command", "cmd"])
+    out = capsys.readouterr().out
+    row = [ln for ln in out.splitlines() if ln.startswith("| 3 |")][0]
+    cells = [c.strip() for c in row.strip("|").split("|")]
+    assert cells[1:] == ["75 %", "76.0"]
+
+
+def test_stage_names_of_every_sweep_variant():
+    base = "void relax::(anonymous namespace)::stage_kernel<{}>(relax::SweepArgs)"
+    assert P._stage_of(base.format("2, true, false")) == (2, True)
+    assert P._stage_of(base.format("4, false, true, false, false, false")) == (4, False)
+    assert P._stage_of(base.format("6, false, true, false, false, true")) == (6, False)  # octilateral
+    assert P._stage_of(base.format("1, false, true, true, false, false")) is None       # diagnostics
+    assert P._short(base.format("5, false, true, false, false, true")) == \
+        "stage_kernel<5, false, true, false, false, true>"
