@@ -484,8 +484,9 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
   __syncthreads();
   // leave the same loads and (dropped) stores in flight, in the same order, as a plane step
   load_b0(pb0);
-  load_window(hi + 1);
+  if constexpr (!NNN) load_window(hi + 1);
   load_point(pb0 - 1);
+  if constexpr (NNN) load_window(hi + 1);
   store_plane(pb0 - 1, false);
 
   // own-node values carried between plane steps: B at q - 1 and q; at q: F' z column,
@@ -631,7 +632,9 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       hi++;
       commit_window(hi);
     }
-    load_window(hi + 1);
+    // the octilateral walk below needs many registers: its sweeps load the next window only
+    // after it, so that the window buffers are not live across it
+    if constexpr (!NNN) load_window(hi + 1);
 
     // 3. current, force and velocity on the tile of plane q = p - 1
     if (qout) {
@@ -878,6 +881,7 @@ __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2))) v
       }
     }
     load_point(p);  // output node of the next plane step
+    if constexpr (NNN) load_window(hi + 1);
     store_plane(q, qout);
     __syncthreads();
 
