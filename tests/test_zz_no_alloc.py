@@ -27,9 +27,9 @@ def _concave_case(n, bc, amp, width):
     return g, x0, B0
 
 
-def _compare(g, x, B0, steps=0, dt=1e-3):
-    cfg = R.make_config(g, dt0=dt, adaptive=False)
-    with context(g, x, B0, dt0=dt, adaptive=False) as r:
+def _compare(g, x, B0, steps=0, dt=1e-3, curl=R.RELAX_CURL_NN):
+    cfg = R.make_config(g, dt0=dt, adaptive=False, curl=curl)
+    with context(g, x, B0, dt0=dt, adaptive=False, curl=curl) as r:
         if steps:
             r.step(steps)
         ref = r.diagnostics()
@@ -57,3 +57,16 @@ def test_noalloc_diagnostics_match_context_three_calls_shrinking():
     banner("noalloc: concave case 20 x 18 x 16, line-tied")
     got = _compare(*_concave_case((20, 18, 16), (0, 0, 0), 0.7, 3.0))
     assert got["concave"] > 0
+
+
+def test_noalloc_diagnostics_octilateral_current():
+    """The same comparison with the octilateral current of Sec. 2.3, whose sweep the entry point
+    runs when the configuration asks for it; xi differs from the nearest-neighbour value, so the
+    octilateral sweep is the one that ran."""
+    for n, bc in (((20, 18, 16), (0, 0, 0)), ((70, 11, 37), (1, 1, 0))):
+        banner(f"noalloc, octilateral: concave case {n}, bc {bc}")
+        case = _concave_case(n, bc, 0.3, 4.0)
+        got = _compare(*case, curl=R.RELAX_CURL_NNN)
+        nn = _compare(*case)
+        assert got["E_M"] == nn["E_M"] and got["min_det"] == nn["min_det"]
+        assert got["xi"] != nn["xi"] and got["R2"] != nn["R2"]
