@@ -35,7 +35,10 @@ def _compile(src: str, verbose: bool, tile_y: int) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(CSRC, f"{src}.ty{tile_y}.o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, f"-DRELAX_TILE_Y={tile_y}", *lang, "-c", path, "-o", obj]
+    # the 64 x 4 build's octilateral sweeps hold 94 KB of LDS, one 4-wave workgroup per CU, so
+    # they cannot reach the two waves per SIMD their attribute asks for; the 64 x 8 build can
+    quiet = ["-Wno-pass-failed"] if tile_y != 8 else []
+    cmd = [HIPCC, *FLAGS, *quiet, f"-DRELAX_TILE_Y={tile_y}", *lang, "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
